@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This package holds no arithmetic of the completion method itself: it only
+produces operator entries, observed index sets and random starting cores.
+"""
+from .generators import (  # noqa: F401
+    WORKLOADS,
+    Workload,
+    green_line_entries,
+    green_planes_entries,
+    morton_decode,
+    make_workload,
+    num_params,
+    random_cores,
+    sample_pairs,
+)

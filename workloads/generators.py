@@ -1,0 +1,217 @@
+"""Seeded synthetic workloads for butterfly-format completion.
+
+The paper's experiments (Sec. 6, "Green's function for Helmholtz equation")
+complete n x n matrices sampled from an oscillatory kernel exp(i w rho)/rho,
+with rho the distance between a source and a receiver point, on a random set
+of observed (row, column) pairs plus a disjoint random test set.  This module
+builds such inputs deterministically:
+
+* ``sample_pairs``: distinct (i, j) pairs drawn without replacement from a
+  PCG64 stream; the first ``nnz`` form the observed set, the next ``ntest``
+  the held-out set (so the two sets are disjoint).
+* ``green_line_entries``: sources x_k = (k/n, 0), receivers y_l = (l/n, 1)
+  (two parallel lines one unit apart), t = exp(+i w rho)/rho.
+* ``green_planes_entries``: sources and receivers on two parallel N x N grids
+  (z = 0 and z = 1), grid points numbered in Morton (Z-curve) order, which
+  stands in for the KD-tree reordering the paper applies so that the matrix
+  has the complementary low-rank property.
+* ``random_cores``: i.i.d. circular complex Gaussian cores, the random
+  initial guess of the ALS iteration.
+
+Nothing here implements the completion method; both the CPU oracle and the
+GPU library receive these arrays as inputs.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+def _log2_int(v: int) -> int:
+    lv = int(v).bit_length() - 1
+    if (1 << lv) != v:
+        raise ValueError(f"{v} is not a power of two")
+    return lv
+
+
+def num_params(n: int, L: int, r: int) -> int:
+    """Complex parameters of an L-level rank-r butterfly of size n: two outer
+    cores of n x r and L inner cores of 2^(L+1) slices of r x r."""
+    return 2 * n * r + L * (2 ** (L + 1)) * r * r
+
+
+def sample_pairs(n: int, nnz: int, ntest: int, seed: int):
+    """Distinct (row, col) pairs: ``nnz`` observed followed by ``ntest`` test.
+
+    Recipe: PCG64(seed) integers in [0, n*n); duplicates dropped keeping the
+    first occurrence; flat index f -> (f // n, f % n).
+    """
+    total = nnz + ntest
+    if total > n * n:
+        raise ValueError("more pairs requested than matrix entries")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    drawn = np.empty(0, dtype=np.int64)
+    want = total
+    while True:
+        extra = int(want * 1.05) + 1024
+        drawn = np.concatenate([drawn, rng.integers(0, n * n, size=extra, dtype=np.int64)])
+        _, first = np.unique(drawn, return_index=True)
+        if first.size >= total:
+            break
+        want = total - first.size
+    first.sort()
+    flat = drawn[first[:total]]
+    rows = (flat // n).astype(np.int32)
+    cols = (flat % n).astype(np.int32)
+    return rows[:nnz], cols[:nnz], rows[nnz:], cols[nnz:]
+
+
+def green_line_entries(n: int, omega: float, rows, cols) -> np.ndarray:
+    """exp(+i w rho)/rho for sources (k/n, 0) and receivers (l/n, 1)."""
+    x = np.asarray(rows, dtype=np.float64) / n
+    y = np.asarray(cols, dtype=np.float64) / n
+    rho = np.sqrt((x - y) ** 2 + 1.0)
+    return np.exp(1j * omega * rho) / rho
+
+
+def morton_decode(k, bits: int):
+    """Split Morton index k (2*bits bits) into grid coordinates (a, b): the
+    odd bits of k form a, the even bits form b."""
+    k = np.asarray(k, dtype=np.int64)
+    a = np.zeros_like(k)
+    b = np.zeros_like(k)
+    for t in range(bits):
+        b |= ((k >> (2 * t)) & 1) << t
+        a |= ((k >> (2 * t + 1)) & 1) << t
+    return a, b
+
+
+def green_planes_entries(n: int, omega: float, rows, cols) -> np.ndarray:
+    """exp(+i w rho)/rho between two N x N grids on [0,1)^2 at z=0 and z=1,
+    N = sqrt(n), grid points numbered in Morton order."""
+    N = int(round(math.isqrt(n)))
+    if N * N != n:
+        raise ValueError("planes geometry needs a square n")
+    bits = _log2_int(N)
+    a1, b1 = morton_decode(rows, bits)
+    a2, b2 = morton_decode(cols, bits)
+    dx = (a1 - a2) / N
+    dy = (b1 - b2) / N
+    rho = np.sqrt(dx * dx + dy * dy + 1.0)
+    return np.exp(1j * omega * rho) / rho
+
+
+def random_cores(n: int, L: int, r: int, seed: int, scale: float = 1.0):
+    """Random starting cores, entries i.i.d. CN(0, 1/r); the first core is
+    multiplied by ``scale`` (callers pass rms(t) * sqrt(r) so that predicted
+    entries have the data's magnitude on average).
+
+    Returns a list: [Z1 (n, r), Z^2..Z^(L+1) (2^(L+1), r, r) each, Z^(L+2) (n, r)].
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sd = math.sqrt(0.5 / r)
+
+    def cn(shape):
+        return sd * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+
+    cores = [cn((n, r)) * scale]
+    for _ in range(L):
+        cores.append(cn((2 ** (L + 1), r, r)))
+    cores.append(cn((n, r)))
+    return cores
+
+
+@dataclass
+class Workload:
+    """One completion instance: sizes, observed entries, test entries, start."""
+
+    name: str
+    n: int
+    L: int
+    r: int
+    omega: float
+    geometry: str
+    nnz: int
+    ntest: int
+    seed: int
+    rows: np.ndarray = field(repr=False, default=None)
+    cols: np.ndarray = field(repr=False, default=None)
+    vals: np.ndarray = field(repr=False, default=None)
+    test_rows: np.ndarray = field(repr=False, default=None)
+    test_cols: np.ndarray = field(repr=False, default=None)
+    test_vals: np.ndarray = field(repr=False, default=None)
+    cores0: list = field(repr=False, default=None)
+
+    @property
+    def c(self) -> int:
+        return self.n >> self.L
+
+
+def _entries(geometry, n, omega, rows, cols):
+    if geometry == "line":
+        return green_line_entries(n, omega, rows, cols)
+    if geometry == "planes":
+        return green_planes_entries(n, omega, rows, cols)
+    raise ValueError(geometry)
+
+
+# name -> (n, L, r, omega, geometry, nnz multiplier k (nnz = k n log2 n), ntest, seed)
+WORKLOADS = {
+    # plain FP64 single instance, random Gaussian start, 20 sweeps
+    "green-line-256": (256, 4, 4, TWO_PI * 16, "line", 4, 1000, 0),
+    # precision workload: complex64 contractions, FP64 solves
+    "green-line-16384": (16384, 8, 6, TWO_PI * 256, "line", 8, 10000, 2),
+    # scale workload: 512 x 512 grids, wavelength of 8 grid cells
+    "green-planes-262144": (262144, 12, 8, TWO_PI * 64, "planes", 4, 100000, 3),
+}
+
+
+def make_workload(name: str, *, n=None, L=None, r=None, omega=None, geometry=None,
+                  nnz=None, ntest=None, seed=None, with_cores=True) -> Workload:
+    """Build a named workload (or a custom one by keyword overrides)."""
+    if name in WORKLOADS:
+        d = WORKLOADS[name]
+        n0, L0, r0, w0, g0, k0, nt0, s0 = d
+        n = n0 if n is None else n
+        L = L0 if L is None else L
+        r = r0 if r is None else r
+        omega = w0 if omega is None else omega
+        geometry = g0 if geometry is None else geometry
+        if nnz is None:
+            nnz = k0 * n * _log2_int(n)
+        ntest = nt0 if ntest is None else ntest
+        seed = s0 if seed is None else seed
+    elif None in (n, L, r, omega, geometry, nnz, ntest, seed):
+        raise ValueError("custom workload needs every size given")
+    if n % (1 << L):
+        raise ValueError("n must be a multiple of 2^L")
+    rows, cols, trows, tcols = sample_pairs(n, nnz, ntest, seed)
+    vals = _entries(geometry, n, omega, rows, cols)
+    tvals = _entries(geometry, n, omega, trows, tcols)
+    w = Workload(name, n, L, r, omega, geometry, nnz, ntest, seed,
+                 rows, cols, vals, trows, tcols, tvals)
+    if with_cores:
+        rms = float(np.sqrt(np.mean(np.abs(vals) ** 2))) if nnz else 1.0
+        w.cores0 = random_cores(n, L, r, seed + 7919, scale=rms * math.sqrt(r))
+    return w
+
+
+def batched_instances(count: int = 64, base_seed: int = 100):
+    """Uneven instances: n from {1024,...,16384} with counts 16/16/16/8/8,
+    leaf size 64 (L = log2(n/64)), w = pi sqrt(n), r = 4 (even id) or 6 (odd id),
+    nnz = 6 n log2 n, seed = base + id."""
+    sizes = [1024] * 16 + [2048] * 16 + [4096] * 16 + [8192] * 8 + [16384] * 8
+    if count != 64:
+        sizes = [sizes[(k * 64) // count] for k in range(count)]
+    out = []
+    for k, n in enumerate(sizes):
+        L = _log2_int(n // 64)
+        r = 4 if k % 2 == 0 else 6
+        out.append(dict(name=f"batch-{k}", n=n, L=L, r=r, omega=math.pi * math.sqrt(n),
+                        geometry="line", nnz=6 * n * _log2_int(n), ntest=1000,
+                        seed=base_seed + k))
+    return out
