@@ -33,9 +33,15 @@ design notes):
   s[a*r + b] = Z[a][b] (row-major reshape, as the algorithm states).
 * Regularization ("a regularization parameter is used to ensure positive
   definiteness", value not given): proximal ridge
-  (K + lam I) s = y + lam s_old with lam = reg_rel * trace(K) / d, d the
-  block's unknown count; ``proximal=False`` gives plain ridge (y on the right).
-  A block with no observed entries keeps its old values.
+  (K + lam I) s = y + lam s_old with lam = max(reg_rel, d * reg_floor) *
+  trace(K) / d, d the block's unknown count; ``proximal=False`` gives plain
+  ridge (y on the right).  ``reg_floor`` is the unit roundoff of the
+  arithmetic that formed K (0 for an exact K; 2^-24 when K is accumulated in
+  FP32), so that rounding cannot make the system indefinite.  Should the
+  Cholesky factorization still fail while lam > 0, lam is raised to
+  max(100 lam, d u trace(K)/d), u = max(reg_floor, 2^-53), up to three times;
+  after that (or at once when lam = 0) the block is reported as not positive
+  definite.  A block with no observed entries keeps its old values.
 * Sweep order: S^1 first, S^(L+2) last (the printed loop bounds and branch
   tests disagree; the text says factors are minimized one at a time).
 
@@ -203,14 +209,16 @@ def _blocks_as_core(blocks, p, L, r):
 
 
 def update_core(cores, p: int, rows, cols, vals, L: int, reg_rel: float = 1e-10,
-                proximal: bool = True):
+                proximal: bool = True, reg_floor: float = 0.0):
     """Return a new core list with core p replaced by its ALS update.
 
     For every block B of core p with at least one observed entry:
-    K = A_B^H A_B, y = A_B^H t_B, lam = reg_rel * trace(K) / d, and
-    (K + lam I) s = y + lam s_old (proximal) or y (plain), solved by Cholesky.
-    Blocks with no entries keep their values.  Raises OracleNotSPD when a
-    regularized K is not positive definite.
+    K = A_B^H A_B, y = A_B^H t_B, lam = max(reg_rel, d reg_floor) trace(K)/d,
+    and (K + lam I) s = y + lam s_old (proximal) or y (plain), solved by
+    Cholesky, with lam raised as described in the module notes when the
+    factorization fails.  Blocks with no entries keep their values.  Raises
+    OracleNotSPD when no regularization in that ladder makes K positive
+    definite.
     """
     rows = np.asarray(rows)
     cols = np.asarray(cols)
@@ -234,13 +242,22 @@ def update_core(cores, p: int, rows, cols, vals, L: int, reg_rel: float = 1e-10,
         AB = A[idx]
         G = AB.conj().T @ AB
         h = AB.conj().T @ t[idx]
-        lam = reg_rel * float(np.trace(G).real) / d
+        tau = float(np.trace(G).real) / d
+        lam = max(reg_rel, d * reg_floor) * tau
+        unit = max(reg_floor, 2.0 ** -53)
+        for attempt in range(4):
+            if attempt > 0:
+                if not lam > 0:
+                    break
+                lam = max(100.0 * lam, d * unit * tau)
+            try:
+                cf = scipy.linalg.cho_factor(G + lam * np.eye(d), lower=True, check_finite=True)
+                break
+            except np.linalg.LinAlgError:
+                cf = None
+        if cf is None:
+            raise OracleNotSPD(f"core {p} block {b}: not positive definite")
         rhs = h + lam * old[b] if proximal else h
-        M = G + lam * np.eye(d)
-        try:
-            cf = scipy.linalg.cho_factor(M, lower=True, check_finite=True)
-        except np.linalg.LinAlgError as exc:
-            raise OracleNotSPD(f"core {p} block {b}: {exc}") from exc
         new[b] = scipy.linalg.cho_solve(cf, rhs)
     out = list(cores)
     out[p] = _blocks_as_core(new, p, L, r)
@@ -248,21 +265,21 @@ def update_core(cores, p: int, rows, cols, vals, L: int, reg_rel: float = 1e-10,
 
 
 def sweep(cores, rows, cols, vals, L: int, reg_rel: float = 1e-10, proximal: bool = True,
-          on_core=None):
+          on_core=None, reg_floor: float = 0.0):
     """One ALS iteration: update S^1, S^2, ..., S^(L+2) in that order.
 
     ``on_core(p, cores)`` is called after each core update (tests use it to
     watch the objective).
     """
     for p in range(L + 2):
-        cores = update_core(cores, p, rows, cols, vals, L, reg_rel, proximal)
+        cores = update_core(cores, p, rows, cols, vals, L, reg_rel, proximal, reg_floor)
         if on_core is not None:
             on_core(p, cores)
     return cores
 
 
 def run_als(cores, rows, cols, vals, L: int, *, tmax: int = 20, eps: float = 1e-3,
-            test=None, reg_rel: float = 1e-10, proximal: bool = True):
+            test=None, reg_rel: float = 1e-10, proximal: bool = True, reg_floor: float = 0.0):
     """Alg. "ALS for Butterfly Completion" with the stopping rule of
     eq. (BF_convergence) checked on the training set after every sweep.
 
@@ -272,7 +289,7 @@ def run_als(cores, rows, cols, vals, L: int, *, tmax: int = 20, eps: float = 1e-
     """
     hist = []
     for it in range(tmax):
-        cores = sweep(cores, rows, cols, vals, L, reg_rel, proximal)
+        cores = sweep(cores, rows, cols, vals, L, reg_rel, proximal, reg_floor=reg_floor)
         rec = {"sweep": it + 1, "train": relative_error(cores, rows, cols, vals, L)}
         if test is not None:
             rec["test"] = relative_error(cores, *test, L)
