@@ -1,0 +1,214 @@
+/*
+ * bfc.h -- C ABI of the MI355X butterfly-completion library (libbfc.so).
+ *
+ * The library completes an n x n complex matrix T from a set of observed
+ * entries (i, j, t_ij) in the tensorized butterfly format of Singh,
+ * Solomonik, Li and Liu, "Efficient Tensor Completion Algorithms for Highly
+ * Oscillatory Operators":
+ *
+ *   n = c * 2^L; row i has digits i_l = floor(i / (c 2^(L-l-1))) mod 2 for
+ *   l < L (i_0 most significant) and i_L = i mod c (Sec. 4.1, eq. (indices));
+ *   same for columns j.
+ *
+ *   Cores (App. A.2, eq. (reshaped_tensors), psi^{-1} most-significant first):
+ *     core 0       Z^1     n x r              row i
+ *     core m=1..L  Z^(m+1) 2^(L+1) x r x r    slice k = psi^{-1}(i_0..i_(L-m), j_0..j_(m-1))
+ *                                             = ((ib >> (m-1)) << m) | (jb >> (L-m)),
+ *                                             ib = i / c, jb = j / c
+ *     core L+1     Z^(L+2) n x r              column j
+ *
+ *   Entry (Sec. 4.1, eq. (BF_tensor_rep)):
+ *     x_ij = Z^1[i] Z^2[k_2] ... Z^(L+1)[k_(L+1)] Z^(L+2)[j]^T
+ *
+ *   Objective (Sec. 5, eq. (BF_objective)): 1/2 ||P_Omega(T - X)||_F^2.
+ *
+ * bfc_sweep_core performs one core update of the ALS method (Sec. 5.1.1,
+ * Alg. "ALS for Butterfly Completion"): every fiber of Z^1 / Z^(L+2) or slice
+ * of an inner core is the solution of the regularized normal equations of
+ * the observed entries it touches,
+ *     (K + lam I) s = y + lam s_old        (proximal, default)
+ *     (K + lam I) s = y                    (ridge)
+ * with K = sum conj(a) a^T, y = sum conj(a) t, lam = reg_rel * trace(K) / d.
+ * A fiber or slice with no observed entry keeps its values.  Inner-core
+ * slices are stored row-major: s[a*r + b] = Z[k][a][b].
+ *
+ * Memory and layout conventions (all calls):
+ *   - Complex numbers are interleaved (re, im) pairs of doubles (complex128)
+ *     at the ABI, whatever the internal precision.
+ *   - Index arrays are int32, values in [0, n).
+ *   - Pointers named d_* are DEVICE pointers (HIP device memory of the
+ *     current device); the caller owns them.  The library copies what it
+ *     needs during bfc_init_cores and keeps no caller pointer afterwards.
+ *   - Every call takes a hipStream_t (as void*, NULL = default stream) and
+ *     enqueues its work there.  bfc_init_cores, bfc_residual and
+ *     bfc_sync_status synchronize that stream before returning; the others
+ *     return as soon as the work is enqueued.
+ *   - Cores layout for get/set/init: core 0 (n*r values, row-major), then
+ *     cores 1..L (2^(L+1)*r*r each, slice-major then row-major), then core
+ *     L+1 (n*r) -- bfc_num_params(n, L, r) complex values in total.
+ *
+ * Errors: every function returns a bfc_status; nothing throws or aborts
+ * across the ABI.  A message for the last error of the calling thread is
+ * returned by bfc_last_error().  Solve failures inside enqueued work (a
+ * block whose regularized K is not positive definite) leave that block's
+ * old values in place and are reported by the next bfc_sync_status or
+ * bfc_residual call on the problem.
+ */
+#ifndef BFC_H
+#define BFC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bfc_status;
+#define BFC_OK 0
+#define BFC_EINVAL 1      /* bad argument: sizes, ranges, null pointers       */
+#define BFC_ENOMEM 2      /* device allocation failed                         */
+#define BFC_EHIP 3        /* a HIP runtime call failed                        */
+#define BFC_ENOTSPD 4     /* a regularized normal-equation matrix was not SPD */
+#define BFC_ENONFINITE 5  /* NaN or Inf in an input value                     */
+
+/* arithmetic modes */
+#define BFC_C128 0        /* complex128 cores and contractions, FP64 Gram, FP64 solves        */
+#define BFC_C64 1         /* complex64 cores and contractions, FP32 Gram, FP64 solves + one
+                             step of iterative refinement                                      */
+#define BFC_C64_BF16GRAM 2 /* as BFC_C64 but the Gram/right-hand-side products take bf16
+                             inputs (FP32 accumulation); the FP64 solve is followed by one
+                             refinement step against the FP32 normal-equation residual
+                             recomputed from the entries                                        */
+
+/* regularization forms (the paper leaves the regularization unspecified) */
+#define BFC_REG_PROXIMAL 0
+#define BFC_REG_RIDGE 1
+
+#define BFC_MAX_RANK 8
+#define BFC_MAX_LEVELS 24
+
+typedef struct bfc_config {
+    int64_t n;          /* matrix size; n = c * 2^L with c >= 1 an integer          */
+    int32_t L;          /* butterfly levels, 0 <= L <= BFC_MAX_LEVELS                */
+    int32_t r;          /* rank, 1 <= r <= BFC_MAX_RANK                              */
+    int32_t precision;  /* BFC_C128, BFC_C64 or BFC_C64_BF16GRAM                     */
+    int32_t reg_mode;   /* BFC_REG_PROXIMAL or BFC_REG_RIDGE                         */
+    double reg_rel;     /* lam = reg_rel * trace(K)/d; >= 0                           */
+    uint64_t seed;      /* random start when bfc_init_cores gets no initial cores    */
+} bfc_config;
+
+typedef struct bfc_problem bfc_problem;
+
+/* Number of complex parameters 2 n r + L 2^(L+1) r^2 (Sec. 3.2). */
+int64_t bfc_num_params(int64_t n, int32_t L, int32_t r);
+
+/*
+ * Build a completion problem from nnz observed entries (d_rows[e], d_cols[e],
+ * d_vals[e]) (Sec. 5, the set Omega of eq. (BF_objective)).  Duplicated
+ * pairs are kept and count as separate least-squares rows.  The library
+ * computes every entry's block keys, sorts a private copy of the entries per
+ * core by block (and, inside inner-core slices, by row or column), and sets
+ * the starting cores: d_cores_init (bfc_num_params complex128 values, layout
+ * above) or, when NULL, i.i.d. complex Gaussian values CN(0, 1/r) drawn from
+ * a counter-based generator keyed by cfg->seed.
+ *
+ * Regularization used by every later core update: with tau = trace(K)/d,
+ * lam = max(reg_rel, d * u_K) * tau where u_K is the unit roundoff of the
+ * Gram accumulation (0 in BFC_C128, 2^-24 in the complex64 modes, so that
+ * FP32 rounding cannot make K + lam I indefinite).  If the FP64 Cholesky
+ * factorization still fails while lam > 0, lam is raised to
+ * max(100 lam, d max(u_K, 2^-53) tau), at most three times.
+ * Returns EINVAL for nnz < 1, a bad config (n not c*2^L, r or L out of
+ * range, negative reg_rel) or an index outside [0, n); ENONFINITE for a
+ * non-finite value; ENOMEM when device memory runs out.  On success *out
+ * owns all device memory of the problem until bfc_destroy.
+ */
+bfc_status bfc_init_cores(const bfc_config* cfg, int64_t nnz,
+                          const int32_t* d_rows, const int32_t* d_cols,
+                          const void* d_vals, const void* d_cores_init,
+                          void* hip_stream, bfc_problem** out);
+
+/*
+ * One ALS core update (Alg. "ALS for Butterfly Completion", one value of its
+ * core loop): core = 0 .. L+1 (the paper's S^(core+1)).  All other cores are
+ * read at their current values.  Asynchronous on hip_stream.
+ */
+bfc_status bfc_sweep_core(bfc_problem* p, int32_t core, void* hip_stream);
+
+/* One full ALS iteration: cores 0, 1, ..., L+1 in that order.  Asynchronous. */
+bfc_status bfc_sweep(bfc_problem* p, void* hip_stream);
+
+/*
+ * x_ij for m listed pairs (eq. (BF_tensor_rep)), written to d_out as m
+ * complex128 values.  m = 0 is allowed (no work).  A pair with an index
+ * outside [0, n) gets NaN (nothing outside the cores is read).  Asynchronous.
+ */
+bfc_status bfc_predict_entries(const bfc_problem* p, int64_t m,
+                               const int32_t* d_rows, const int32_t* d_cols,
+                               void* d_out, void* hip_stream);
+
+/*
+ * out_sq[0] = sum |t - x|^2 and out_sq[1] = sum |t|^2 over m listed entries
+ * (the two norms of eq. (BF_convergence)), accumulated in FP64 in a fixed
+ * order (bitwise reproducible); an index outside [0, n) makes out_sq[0] NaN.
+ * out_sq is HOST memory.  Synchronizes.
+ * Also reports (and clears) pending solve failures: returns ENOTSPD after
+ * filling out_sq if any block failed since the last report.
+ */
+bfc_status bfc_residual(const bfc_problem* p, int64_t m, const int32_t* d_rows,
+                        const int32_t* d_cols, const void* d_vals, double out_sq[2],
+                        void* hip_stream);
+
+/* Copy the cores out to / in from d_cores (bfc_num_params complex128 values). */
+bfc_status bfc_get_cores(const bfc_problem* p, void* d_cores, void* hip_stream);
+bfc_status bfc_set_cores(bfc_problem* p, const void* d_cores, void* hip_stream);
+
+/* Synchronize hip_stream and report (and clear) pending solve failures. */
+bfc_status bfc_sync_status(bfc_problem* p, void* hip_stream);
+
+/*
+ * Solve counters since the problem was created or last reset: out[0] =
+ * blocks whose system stayed not positive definite (they kept their old
+ * values; bfc_sync_status / bfc_residual report and clear this count), out[1]
+ * = blocks solved only after the regularization was raised (see
+ * bfc_init_cores for the ladder).  Synchronizes hip_stream; reset != 0 clears
+ * both counts.
+ */
+bfc_status bfc_solve_counters(bfc_problem* p, int32_t reset, int64_t out[2], void* hip_stream);
+
+/*
+ * Per-kernel timing with HIP events, for benchmarks and profiling.  When
+ * enabled, every launch of the kinds below is bracketed by two events on the
+ * launch's stream.  bfc_profile_enable synchronizes the device and resets the
+ * counters; bfc_profile_read waits for the recorded events and returns the
+ * summed elapsed time (ms) and the launch count of one kind since the reset.
+ */
+#define BFC_KERNEL_OUTER 0        /* outer-core fiber update (Gram, RHS and solve fused) */
+#define BFC_KERNEL_INNER_GRAM 1   /* inner-core Gram / right-hand-side partial products   */
+#define BFC_KERNEL_INNER_SOLVE 2  /* inner-core slice solves                              */
+#define BFC_KERNEL_RESIDUAL 3     /* residual norms                                       */
+#define BFC_KERNEL_PREDICT 4      /* entry reconstruction                                 */
+bfc_status bfc_profile_enable(bfc_problem* p, int32_t enable);
+bfc_status bfc_profile_read(bfc_problem* p, int32_t kind, double* total_ms, int64_t* launches);
+
+/*
+ * Layout figures of one core, for work accounting: out[0] = blocks (fibers
+ * or slices); for an inner core out[1] = runs (distinct (slice, row) pairs,
+ * or (slice, column) pairs, holding entries), out[2] = subgroups (runs cut
+ * into pieces of at most 8 entries), out[3] = Gram work items (wavefronts),
+ * out[4] = 1 if the core groups by row, 0 by column; for an outer core
+ * out[1..3] = 0 and out[4] = -1.
+ */
+bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[5]);
+
+/* Release every device allocation of the problem.  NULL is ignored. */
+void bfc_destroy(bfc_problem* p);
+
+/* Message describing the calling thread's last error ("" if none). */
+const char* bfc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFC_H */

@@ -1,0 +1,30 @@
+"""MI355X-native ALS completion in the tensorized butterfly format.
+
+The compute path is libbfc.so (HIP kernels for gfx950 behind a C ABI, see
+include/bfc.h); this package is its Python binding.  Importing the package
+does not load the library; the first call does, and fails loudly if it has
+not been built.
+"""
+from .api import (  # noqa: F401
+    BfcError,
+    Config,
+    core_stats,
+    profile_enable,
+    profile_read,
+    Problem,
+    destroy,
+    flatten_cores,
+    get_cores,
+    init_cores,
+    last_error,
+    num_params,
+    predict_entries,
+    relative_error,
+    residual,
+    set_cores,
+    solve_counters,
+    sweep,
+    sweep_core,
+    sync_status,
+    unflatten_cores,
+)

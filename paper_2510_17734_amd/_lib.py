@@ -1,0 +1,114 @@
+"""ctypes declarations of libbfc's C ABI (include/bfc.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbfc.so")
+
+BFC_OK = 0
+BFC_EINVAL = 1
+BFC_ENOMEM = 2
+BFC_EHIP = 3
+BFC_ENOTSPD = 4
+BFC_ENONFINITE = 5
+
+STATUS_NAMES = {
+    BFC_OK: "OK",
+    BFC_EINVAL: "EINVAL",
+    BFC_ENOMEM: "ENOMEM",
+    BFC_EHIP: "EHIP",
+    BFC_ENOTSPD: "ENOTSPD",
+    BFC_ENONFINITE: "ENONFINITE",
+}
+
+BFC_C128 = 0
+BFC_C64 = 1
+BFC_C64_BF16GRAM = 2
+BFC_REG_PROXIMAL = 0
+BFC_REG_RIDGE = 1
+
+# every symbol include/bfc.h declares
+EXPORTS = (
+    "bfc_num_params",
+    "bfc_init_cores",
+    "bfc_sweep_core",
+    "bfc_sweep",
+    "bfc_predict_entries",
+    "bfc_residual",
+    "bfc_get_cores",
+    "bfc_set_cores",
+    "bfc_sync_status",
+    "bfc_destroy",
+    "bfc_last_error",
+    "bfc_profile_enable",
+    "bfc_profile_read",
+    "bfc_core_stats",
+    "bfc_solve_counters",
+)
+
+KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4}
+
+
+class BfcConfig(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("L", ctypes.c_int32),
+        ("r", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("reg_mode", ctypes.c_int32),
+        ("reg_rel", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libbfc.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.c_void_p
+    lib.bfc_num_params.argtypes = [i64, i32, i32]
+    lib.bfc_num_params.restype = i64
+    lib.bfc_init_cores.argtypes = [ctypes.POINTER(BfcConfig), i64, vp, vp, vp, vp, vp,
+                                   ctypes.POINTER(P)]
+    lib.bfc_init_cores.restype = i32
+    lib.bfc_sweep_core.argtypes = [P, i32, vp]
+    lib.bfc_sweep_core.restype = i32
+    lib.bfc_sweep.argtypes = [P, vp]
+    lib.bfc_sweep.restype = i32
+    lib.bfc_predict_entries.argtypes = [P, i64, vp, vp, vp, vp]
+    lib.bfc_predict_entries.restype = i32
+    lib.bfc_residual.argtypes = [P, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_residual.restype = i32
+    lib.bfc_get_cores.argtypes = [P, vp, vp]
+    lib.bfc_get_cores.restype = i32
+    lib.bfc_set_cores.argtypes = [P, vp, vp]
+    lib.bfc_set_cores.restype = i32
+    lib.bfc_sync_status.argtypes = [P, vp]
+    lib.bfc_sync_status.restype = i32
+    lib.bfc_destroy.argtypes = [P]
+    lib.bfc_destroy.restype = None
+    lib.bfc_profile_enable.argtypes = [P, i32]
+    lib.bfc_profile_enable.restype = i32
+    lib.bfc_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.bfc_profile_read.restype = i32
+    lib.bfc_core_stats.argtypes = [P, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.bfc_core_stats.restype = i32
+    lib.bfc_solve_counters.argtypes = [P, i32, ctypes.POINTER(ctypes.c_int64), vp]
+    lib.bfc_solve_counters.restype = i32
+    lib.bfc_last_error.argtypes = []
+    lib.bfc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib

@@ -1,0 +1,241 @@
+"""Python binding of libbfc: argument marshalling only.
+
+Every function here forwards to the C ABI of the same name (include/bfc.h);
+all arithmetic of the completion method runs in the library's HIP kernels.
+PyTorch provides device memory (the tensors passed in) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (BFC_C128, BFC_C64, BFC_C64_BF16GRAM, BFC_REG_PROXIMAL, BFC_REG_RIDGE,
+                   STATUS_NAMES)
+
+PRECISIONS = {"c128": BFC_C128, "c64": BFC_C64, "bf16gram": BFC_C64_BF16GRAM}
+REG_MODES = {"proximal": BFC_REG_PROXIMAL, "ridge": BFC_REG_RIDGE}
+
+
+class BfcError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = _lib.load()
+        msg = lib.bfc_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise BfcError(code, where)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev_i32(x, device) -> torch.Tensor:
+    t = torch.as_tensor(x)
+    if t.dtype != torch.int32:
+        t = t.to(torch.int32)
+    return t.to(device).contiguous()
+
+
+def _dev_c128(x, device) -> torch.Tensor:
+    t = torch.as_tensor(x)
+    if t.dtype != torch.complex128:
+        t = t.to(torch.complex128)
+    return t.to(device).contiguous()
+
+
+def num_params(n: int, L: int, r: int) -> int:
+    return int(_lib.load().bfc_num_params(n, L, r))
+
+
+def flatten_cores(cores) -> np.ndarray:
+    """[Z^1, Z^2..Z^(L+1), Z^(L+2)] -> one complex128 vector in the ABI layout."""
+    return np.concatenate([np.asarray(z, dtype=np.complex128).ravel() for z in cores])
+
+
+def unflatten_cores(flat, n: int, L: int, r: int):
+    """Inverse of flatten_cores."""
+    flat = np.asarray(flat)
+    out, off = [], 0
+    shapes = [(n, r)] + [(2 ** (L + 1), r, r)] * L + [(n, r)]
+    for s in shapes:
+        size = int(np.prod(s))
+        out.append(flat[off:off + size].reshape(s))
+        off += size
+    return out
+
+
+@dataclass
+class Config:
+    n: int
+    L: int
+    r: int
+    precision: str = "c128"
+    reg_mode: str = "proximal"
+    reg_rel: float = 1e-10
+    seed: int = 0
+
+    def to_c(self) -> _lib.BfcConfig:
+        return _lib.BfcConfig(self.n, self.L, self.r, PRECISIONS[self.precision],
+                              REG_MODES[self.reg_mode], float(self.reg_rel), int(self.seed))
+
+
+class Problem:
+    """Owns a bfc_problem handle (device memory freed on close / garbage collection)."""
+
+    def __init__(self, handle, cfg: Config, nnz: int, device):
+        self._h = handle
+        self.cfg = cfg
+        self.nnz = nnz
+        self.device = device
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("problem already destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _lib.load().bfc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def init_cores(cfg: Config, rows, cols, vals, cores_init=None, *, device="cuda:0",
+               stream=None) -> Problem:
+    """bfc_init_cores: lay out the observed entries and set the starting cores."""
+    lib = _lib.load()
+    device = torch.device(device)
+    r_t = _dev_i32(rows, device)
+    c_t = _dev_i32(cols, device)
+    v_t = _dev_c128(vals, device)
+    ci = None
+    if cores_init is not None:
+        if isinstance(cores_init, (list, tuple)):
+            cores_init = flatten_cores(cores_init)
+        ci = _dev_c128(cores_init, device)
+        if ci.numel() != lib.bfc_num_params(cfg.n, cfg.L, cfg.r):
+            raise ValueError("cores_init has the wrong number of values")
+    h = ctypes.c_void_p()
+    cc = cfg.to_c()
+    with torch.cuda.device(device):
+        code = lib.bfc_init_cores(ctypes.byref(cc), int(r_t.numel()), _ptr(r_t), _ptr(c_t),
+                                  _ptr(v_t), _ptr(ci), _stream(stream), ctypes.byref(h))
+    _check(code, "bfc_init_cores")
+    return Problem(h, cfg, int(r_t.numel()), device)
+
+
+def sweep_core(p: Problem, core: int, stream=None):
+    """bfc_sweep_core: one ALS core update (asynchronous)."""
+    _check(_lib.load().bfc_sweep_core(p.handle, int(core), _stream(stream)), "bfc_sweep_core")
+
+
+def sweep(p: Problem, stream=None):
+    """bfc_sweep: cores 0..L+1 in order (asynchronous)."""
+    _check(_lib.load().bfc_sweep(p.handle, _stream(stream)), "bfc_sweep")
+
+
+def predict_entries(p: Problem, rows, cols, out=None, stream=None) -> torch.Tensor:
+    """bfc_predict_entries: complex128 predictions on the listed pairs."""
+    r_t = _dev_i32(rows, p.device)
+    c_t = _dev_i32(cols, p.device)
+    m = int(r_t.numel())
+    if out is None:
+        out = torch.empty(m, dtype=torch.complex128, device=p.device)
+    _check(_lib.load().bfc_predict_entries(p.handle, m, _ptr(r_t), _ptr(c_t), _ptr(out),
+                                           _stream(stream)), "bfc_predict_entries")
+    return out
+
+
+def residual(p: Problem, rows, cols, vals, stream=None):
+    """bfc_residual: (sum |t - x|^2, sum |t|^2) in FP64; raises on pending solve failures."""
+    r_t = _dev_i32(rows, p.device)
+    c_t = _dev_i32(cols, p.device)
+    v_t = _dev_c128(vals, p.device)
+    out = (ctypes.c_double * 2)()
+    _check(_lib.load().bfc_residual(p.handle, int(r_t.numel()), _ptr(r_t), _ptr(c_t), _ptr(v_t),
+                                    out, _stream(stream)), "bfc_residual")
+    return float(out[0]), float(out[1])
+
+
+def relative_error(p: Problem, rows, cols, vals, stream=None) -> float:
+    num, den = residual(p, rows, cols, vals, stream)
+    return (num / den) ** 0.5 if den > 0 else num ** 0.5
+
+
+def get_cores(p: Problem, out=None, stream=None) -> torch.Tensor:
+    lib = _lib.load()
+    m = int(lib.bfc_num_params(p.cfg.n, p.cfg.L, p.cfg.r))
+    if out is None:
+        out = torch.empty(m, dtype=torch.complex128, device=p.device)
+    _check(lib.bfc_get_cores(p.handle, _ptr(out), _stream(stream)), "bfc_get_cores")
+    return out
+
+
+def set_cores(p: Problem, cores, stream=None):
+    if isinstance(cores, (list, tuple)):
+        cores = flatten_cores(cores)
+    t = _dev_c128(cores, p.device)
+    _check(_lib.load().bfc_set_cores(p.handle, _ptr(t), _stream(stream)), "bfc_set_cores")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+
+def sync_status(p: Problem, stream=None):
+    _check(_lib.load().bfc_sync_status(p.handle, _stream(stream)), "bfc_sync_status")
+
+
+def destroy(p: Problem):
+    p.close()
+
+
+def last_error() -> str:
+    return _lib.load().bfc_last_error().decode(errors="replace")
+
+
+def profile_enable(p: Problem, enable: bool = True):
+    """bfc_profile_enable: start (or stop) per-kernel event timing, reset counters."""
+    _check(_lib.load().bfc_profile_enable(p.handle, 1 if enable else 0), "bfc_profile_enable")
+
+
+def profile_read(p: Problem, kind: str):
+    """bfc_profile_read: (total ms, launches) of one kernel kind since the reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.load().bfc_profile_read(p.handle, _lib.KERNEL_KINDS[kind], ctypes.byref(ms),
+                                        ctypes.byref(n)), "bfc_profile_read")
+    return float(ms.value), int(n.value)
+
+
+def core_stats(p: Problem, core: int):
+    """bfc_core_stats: blocks, subgroups, work items, grouping of one core."""
+    out = (ctypes.c_int64 * 5)()
+    _check(_lib.load().bfc_core_stats(p.handle, int(core), out), "bfc_core_stats")
+    return {"blocks": out[0], "runs": out[1], "subgroups": out[2], "items": out[3],
+            "by_row": out[4]}
+
+
+def solve_counters(p: Problem, reset: bool = False, stream=None):
+    """bfc_solve_counters: (failed blocks pending report, blocks solved with raised lam)."""
+    out = (ctypes.c_int64 * 2)()
+    _check(_lib.load().bfc_solve_counters(p.handle, 1 if reset else 0, out, _stream(stream)),
+           "bfc_solve_counters")
+    return int(out[0]), int(out[1])

@@ -1,0 +1,379 @@
+// extern "C" entry points of libbfc (declared in include/bfc.h).
+#include <cstring>
+#include <new>
+
+#include "bfc_device.h"
+
+namespace bfc {
+
+size_t inner_partial_bytes(int prec, int r);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? BFC_ENOMEM : BFC_EHIP;
+  }
+  P->allocs.push_back(*ptr);
+  return BFC_OK;
+}
+
+hipEvent_t Profiler::take() {
+  if (pool.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = pool.back();
+  pool.pop_back();
+  return e;
+}
+
+ProfScope::ProfScope(Profiler* pr_, int kind_, hipStream_t st_) : pr(pr_), kind(kind_), st(st_) {
+  if (!pr->on) return;
+  a = pr->take();
+  b = pr->take();
+  if (a && b && hipEventRecord(a, st) == hipSuccess) return;
+  a = b = nullptr;
+}
+
+ProfScope::~ProfScope() {
+  if (!a || !b) return;
+  if (hipEventRecord(b, st) == hipSuccess) pr->pending[kind].push_back({a, b});
+}
+
+}  // namespace bfc
+
+struct bfc_problem : public bfc::Problem {};
+
+namespace bfc {
+
+static void release_events(Profiler& pr) {
+  for (auto& v : pr.pending)
+    for (auto& ab : v) {
+      (void)hipEventDestroy(ab.first);
+      (void)hipEventDestroy(ab.second);
+    }
+  for (auto& v : pr.pending) v.clear();
+  for (hipEvent_t e : pr.pool) (void)hipEventDestroy(e);
+  pr.pool.clear();
+}
+
+static void free_problem(bfc_problem* P) {
+  release_events(P->prof);
+  for (void* p : P->allocs) (void)hipFree(p);
+  P->allocs.clear();
+  if (P->red_host) (void)hipHostFree(P->red_host);
+  P->red_host = nullptr;
+  delete P;
+}
+
+static bfc_status check_config(const bfc_config* cfg, int32_t* c_out) {
+  if (!cfg) {
+    set_error("null config");
+    return BFC_EINVAL;
+  }
+  if (cfg->L < 0 || cfg->L > BFC_MAX_LEVELS) {
+    set_error("L out of range");
+    return BFC_EINVAL;
+  }
+  if (cfg->r < 1 || cfg->r > BFC_MAX_RANK) {
+    set_error("r out of range [1, 8]");
+    return BFC_EINVAL;
+  }
+  const int64_t two_l = (int64_t)1 << cfg->L;
+  if (cfg->n < 1 || cfg->n % two_l != 0 || cfg->n > 0x7FFFFFFF) {
+    set_error("n must be a positive multiple of 2^L below 2^31");
+    return BFC_EINVAL;
+  }
+  if (cfg->precision != BFC_C128 && cfg->precision != BFC_C64 &&
+      cfg->precision != BFC_C64_BF16GRAM) {
+    set_error("unknown precision");
+    return BFC_EINVAL;
+  }
+  if (cfg->precision == BFC_C64_BF16GRAM) {
+    set_error("BFC_C64_BF16GRAM is not available in this build");
+    return BFC_EINVAL;
+  }
+  if (cfg->reg_mode != BFC_REG_PROXIMAL && cfg->reg_mode != BFC_REG_RIDGE) {
+    set_error("unknown regularization mode");
+    return BFC_EINVAL;
+  }
+  if (!(cfg->reg_rel >= 0.0)) {
+    set_error("reg_rel must be >= 0");
+    return BFC_EINVAL;
+  }
+  *c_out = (int32_t)(cfg->n / two_l);
+  return BFC_OK;
+}
+
+}  // namespace bfc
+
+using namespace bfc;
+
+extern "C" {
+
+int64_t bfc_num_params(int64_t n, int32_t L, int32_t r) { return bfc::num_params(n, L, r); }
+
+const char* bfc_last_error(void) { return g_last_error.c_str(); }
+
+bfc_status bfc_init_cores(const bfc_config* cfg, int64_t nnz, const int32_t* d_rows,
+                          const int32_t* d_cols, const void* d_vals, const void* d_cores_init,
+                          void* hip_stream, bfc_problem** out) {
+  set_error("");
+  if (!out) {
+    set_error("null output pointer");
+    return BFC_EINVAL;
+  }
+  *out = nullptr;
+  int32_t c = 0;
+  BFC_TRY(check_config(cfg, &c));
+  if (nnz < 1 || nnz > 0x7FFFFFFF) {
+    set_error("nnz must be in [1, 2^31)");
+    return BFC_EINVAL;
+  }
+  if (!d_rows || !d_cols || !d_vals) {
+    set_error("null entry array");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  bfc_problem* P = new (std::nothrow) bfc_problem();
+  if (!P) {
+    set_error("host allocation failed");
+    return BFC_ENOMEM;
+  }
+  P->cfg = *cfg;
+  P->n = cfg->n;
+  P->L = cfg->L;
+  P->r = cfg->r;
+  P->c = c;
+  P->prec = cfg->precision;
+  P->nnz = nnz;
+  P->elem = P->prec == BFC_C128 ? 16 : 8;
+  P->nparams = num_params(P->n, P->L, P->r);
+  bfc_status s = BFC_OK;
+  auto fail = [&](bfc_status code) {
+    free_problem(P);
+    return code;
+  };
+  if ((s = dev_alloc(P, &P->cores, P->nparams * P->elem)) != BFC_OK) return fail(s);
+  if ((s = dev_alloc(P, (void**)&P->flags, 64)) != BFC_OK) return fail(s);
+  P->red_len = 2 * 2048;
+  if ((s = dev_alloc(P, (void**)&P->red, (P->red_len + 2) * sizeof(double))) != BFC_OK)
+    return fail(s);
+  if (hipHostMalloc((void**)&P->red_host, 2 * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    set_error("hipHostMalloc failed");
+    return fail(BFC_ENOMEM);
+  }
+  if (hipMemsetAsync(P->flags, 0, 64, st) != hipSuccess) {
+    set_error("hipMemsetAsync failed");
+    return fail(BFC_EHIP);
+  }
+  if ((s = build_layout(P, d_rows, d_cols, d_vals, st)) != BFC_OK) return fail(s);
+  if (P->max_items > 0) {
+    P->partials_bytes = (size_t)P->max_items * inner_partial_bytes(P->prec, P->r);
+    if ((s = dev_alloc(P, &P->partials, P->partials_bytes)) != BFC_OK) return fail(s);
+  }
+  if (d_cores_init)
+    s = launch_convert_cores(P, d_cores_init, nullptr, true, st);
+  else
+    s = launch_random_cores(P, cfg->seed, st);
+  if (s != BFC_OK) return fail(s);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    set_error("hipStreamSynchronize failed");
+    return fail(BFC_EHIP);
+  }
+  *out = P;
+  return BFC_OK;
+}
+
+bfc_status bfc_sweep_core(bfc_problem* p, int32_t core, void* hip_stream) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  if (core < 0 || core > p->L + 1) {
+    set_error("core index out of range [0, L+1]");
+    return BFC_EINVAL;
+  }
+  return launch_sweep_core(p, core, (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_sweep(bfc_problem* p, void* hip_stream) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  for (int core = 0; core <= p->L + 1; ++core)
+    BFC_TRY(launch_sweep_core(p, core, (hipStream_t)hip_stream));
+  return BFC_OK;
+}
+
+bfc_status bfc_predict_entries(const bfc_problem* p, int64_t m, const int32_t* d_rows,
+                               const int32_t* d_cols, void* d_out, void* hip_stream) {
+  if (!p || m < 0 || (m > 0 && (!d_rows || !d_cols || !d_out))) {
+    set_error("bad predict arguments");
+    return BFC_EINVAL;
+  }
+  return launch_predict(p, m, d_rows, d_cols, d_out, (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_residual(const bfc_problem* p, int64_t m, const int32_t* d_rows,
+                        const int32_t* d_cols, const void* d_vals, double out_sq[2],
+                        void* hip_stream) {
+  if (!p || m < 0 || !out_sq || (m > 0 && (!d_rows || !d_cols || !d_vals))) {
+    set_error("bad residual arguments");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* dres = p->red + p->red_len;
+  if (m == 0) {
+    out_sq[0] = out_sq[1] = 0.0;
+  } else {
+    BFC_TRY(launch_residual(p, m, d_rows, d_cols, d_vals, dres, st));
+    BFC_HIP_TRY(hipMemcpyAsync(p->red_host, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  int32_t nfail = 0;
+  BFC_HIP_TRY(hipMemcpyAsync(&nfail, p->flags, 4, hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  if (m > 0) {
+    out_sq[0] = p->red_host[0];
+    out_sq[1] = p->red_host[1];
+  }
+  if (nfail) {
+    BFC_HIP_TRY(hipMemsetAsync(p->flags, 0, 4, st));
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+    set_error("a regularized normal-equation matrix was not positive definite (" +
+              std::to_string(nfail) + " blocks kept their values)");
+    return BFC_ENOTSPD;
+  }
+  return BFC_OK;
+}
+
+bfc_status bfc_get_cores(const bfc_problem* p, void* d_cores, void* hip_stream) {
+  if (!p || !d_cores) {
+    set_error("bad get_cores arguments");
+    return BFC_EINVAL;
+  }
+  return launch_convert_cores(const_cast<bfc_problem*>(p), nullptr, d_cores, false,
+                              (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_set_cores(bfc_problem* p, const void* d_cores, void* hip_stream) {
+  if (!p || !d_cores) {
+    set_error("bad set_cores arguments");
+    return BFC_EINVAL;
+  }
+  return launch_convert_cores(p, d_cores, nullptr, true, (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_sync_status(bfc_problem* p, void* hip_stream) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  int32_t nfail = 0;
+  BFC_HIP_TRY(hipMemcpyAsync(&nfail, p->flags, 4, hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  if (nfail) {
+    BFC_HIP_TRY(hipMemsetAsync(p->flags, 0, 4, st));
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+    set_error("a regularized normal-equation matrix was not positive definite (" +
+              std::to_string(nfail) + " blocks kept their values)");
+    return BFC_ENOTSPD;
+  }
+  return BFC_OK;
+}
+
+bfc_status bfc_profile_enable(bfc_problem* p, int32_t enable) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  BFC_HIP_TRY(hipDeviceSynchronize());
+  Profiler& pr = p->prof;
+  for (auto& v : pr.pending) {
+    for (auto& ab : v) {
+      pr.pool.push_back(ab.first);
+      pr.pool.push_back(ab.second);
+    }
+    v.clear();
+  }
+  for (int k = 0; k < KIND_COUNT; ++k) {
+    pr.total_ms[k] = 0.0;
+    pr.launches[k] = 0;
+  }
+  pr.on = enable != 0;
+  return BFC_OK;
+}
+
+bfc_status bfc_profile_read(bfc_problem* p, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!p || kind < 0 || kind >= KIND_COUNT || !total_ms || !launches) {
+    set_error("bad profile_read arguments");
+    return BFC_EINVAL;
+  }
+  Profiler& pr = p->prof;
+  for (int k = 0; k < KIND_COUNT; ++k) {
+    for (auto& ab : pr.pending[k]) {
+      BFC_HIP_TRY(hipEventSynchronize(ab.second));
+      float ms = 0.f;
+      BFC_HIP_TRY(hipEventElapsedTime(&ms, ab.first, ab.second));
+      pr.total_ms[k] += ms;
+      pr.launches[k] += 1;
+      pr.pool.push_back(ab.first);
+      pr.pool.push_back(ab.second);
+    }
+    pr.pending[k].clear();
+  }
+  *total_ms = pr.total_ms[kind];
+  *launches = pr.launches[kind];
+  return BFC_OK;
+}
+
+bfc_status bfc_solve_counters(bfc_problem* p, int32_t reset, int64_t out[2], void* hip_stream) {
+  if (!p || !out) {
+    set_error("bad solve_counters arguments");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  int32_t h[2] = {0, 0};
+  BFC_HIP_TRY(hipMemcpyAsync(h, p->flags, 8, hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  out[0] = h[0];
+  out[1] = h[1];
+  if (reset) {
+    BFC_HIP_TRY(hipMemsetAsync(p->flags, 0, 8, st));
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+  }
+  return BFC_OK;
+}
+
+bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[5]) {
+  if (!p || !out || core < 0 || core > p->L + 1) {
+    set_error("bad core_stats arguments");
+    return BFC_EINVAL;
+  }
+  const CoreLayout& C = p->lay[core];
+  const bool inner = core >= 1 && core <= p->L;
+  out[0] = C.nblocks;
+  out[1] = inner ? C.nruns : 0;
+  out[2] = inner ? C.nsub : 0;
+  out[3] = inner ? C.nitems : 0;
+  out[4] = inner ? C.group_by_row : -1;
+  return BFC_OK;
+}
+
+void bfc_destroy(bfc_problem* p) {
+  if (p) free_problem(p);
+}
+
+}  // extern "C"

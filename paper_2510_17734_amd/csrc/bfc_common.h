@@ -1,0 +1,157 @@
+// Internal declarations shared by the HIP sources of libbfc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bfc.h"
+
+namespace bfc {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+struct Status {
+  bfc_status code = BFC_OK;
+  std::string msg;
+};
+
+#define BFC_HIP_TRY(expr)                                                   \
+  do {                                                                      \
+    hipError_t _e = (expr);                                                 \
+    if (_e != hipSuccess) {                                                 \
+      ::bfc::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));  \
+      return (_e == hipErrorOutOfMemory) ? BFC_ENOMEM : BFC_EHIP;           \
+    }                                                                       \
+  } while (0)
+
+#define BFC_TRY(expr)                \
+  do {                               \
+    bfc_status _s = (expr);          \
+    if (_s != BFC_OK) return _s;     \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// complex helpers (interleaved re/im)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__host__ __device__ inline cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// acc += a * b
+template <typename T>
+__host__ __device__ inline void cfma(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+template <typename T>
+__host__ __device__ inline void cfma_conj(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+
+// ---------------------------------------------------------------------------
+// problem state
+// ---------------------------------------------------------------------------
+struct WorkItem {   // a run of subgroups of one inner-core slice, one wavefront
+  int32_t tile, sub0, sub1, pad;
+};
+
+struct CoreLayout {
+  int32_t nblocks = 0;
+  int32_t* rows = nullptr;     // entries sorted for this core
+  int32_t* cols = nullptr;
+  void* vals = nullptr;        // compute precision complex
+  int32_t* blk_off = nullptr;  // nblocks + 1
+  // inner cores only
+  int32_t group_by_row = 1;
+  int32_t group_extent = 1;    // rows (or columns) per slice tile
+  int32_t nruns = 0;           // distinct (slice, row|column) pairs with entries
+  int32_t nsub = 0;
+  int32_t* sub_off = nullptr;  // nsub + 1
+  int32_t nitems = 0;
+  WorkItem* items = nullptr;
+  int32_t* tile_items = nullptr;  // nblocks + 1: item range of each slice
+};
+
+// per-kernel timing with HIP events (enabled by bfc_profile_enable)
+enum { KIND_OUTER = 0, KIND_INNER_GRAM = 1, KIND_INNER_SOLVE = 2, KIND_RESIDUAL = 3,
+       KIND_PREDICT = 4, KIND_COUNT = 5 };
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KIND_COUNT];
+  double total_ms[KIND_COUNT] = {0, 0, 0, 0, 0};
+  int64_t launches[KIND_COUNT] = {0, 0, 0, 0, 0};
+  hipEvent_t take();
+};
+
+// Records a start event on construction and a stop event on destruction
+// around the kernel launches of one kind, when profiling is on.
+struct ProfScope {
+  Profiler* pr;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(Profiler* pr_, int kind_, hipStream_t st_);
+  ~ProfScope();
+};
+
+struct Problem {
+  mutable Profiler prof;
+  bfc_config cfg{};
+  int64_t n = 0;
+  int32_t L = 0, r = 0, c = 0;
+  int32_t prec = BFC_C128;
+  int64_t nnz = 0;
+  size_t elem = 16;                  // bytes of one complex compute value
+  void* cores = nullptr;             // compute precision
+  std::vector<int64_t> core_off;     // complex element offset of each core
+  int64_t nparams = 0;
+  std::vector<CoreLayout> lay;       // L+2
+  void* partials = nullptr;          // inner Gram partial sums
+  size_t partials_bytes = 0;
+  int32_t* flags = nullptr;          // [0] solve failures since last report
+  double* red = nullptr;             // residual reduction scratch
+  size_t red_len = 0;
+  double* red_host = nullptr;        // pinned, 2 doubles
+  std::vector<void*> allocs;         // everything hipMalloc'd
+  int32_t max_items = 0;
+};
+
+bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes);
+
+// geometry helpers (host)
+inline int64_t num_params(int64_t n, int L, int r) {
+  return 2 * n * r + (int64_t)L * (int64_t(1) << (L + 1)) * r * r;
+}
+
+// kernel entry points (defined in the .hip sources)
+bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols,
+                        const void* d_vals, hipStream_t st);
+bfc_status launch_sweep_core(Problem* P, int core, hipStream_t st);
+bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
+                          void* out, hipStream_t st);
+bfc_status launch_residual(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
+                           const void* vals, double* out2, hipStream_t st);
+bfc_status launch_convert_cores(Problem* P, const void* src_c128, void* dst_c128, bool to_internal,
+                                hipStream_t st);
+bfc_status launch_random_cores(Problem* P, uint64_t seed, hipStream_t st);
+
+}  // namespace bfc

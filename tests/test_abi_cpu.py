@@ -1,0 +1,83 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2510_17734_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfc.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bfc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_exports():
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_config_struct_layout():
+    # int64 n, int32 L, r, precision, reg_mode, double reg_rel, uint64 seed
+    assert ctypes.sizeof(_lib.BfcConfig) == 40
+    assert _lib.BfcConfig.reg_rel.offset == 24
+
+
+def test_num_params():
+    lib = _lib.load()
+    assert lib.bfc_num_params(256, 4, 4) == 2 * 256 * 4 + 4 * 32 * 16
+    assert lib.bfc_num_params(16384, 8, 6) == 2 * 16384 * 6 + 8 * 512 * 36
+
+
+def _init(cfg, nnz=10, rows=1, cols=1, vals=1):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    fake = lambda v: ctypes.c_void_p(0x1000 if v else 0)  # never dereferenced: rejected first
+    code = lib.bfc_init_cores(None if cfg is None else ctypes.byref(cfg), nnz, fake(rows),
+                              fake(cols), fake(vals), None, None, ctypes.byref(h))
+    return code, lib.bfc_last_error().decode(), h.value
+
+
+@pytest.mark.parametrize("cfg,why", [
+    (None, "null config"),
+    (_lib.BfcConfig(256, 4, 0, 0, 0, 1e-10, 0), "r"),
+    (_lib.BfcConfig(256, 4, 9, 0, 0, 1e-10, 0), "r"),
+    (_lib.BfcConfig(250, 4, 4, 0, 0, 1e-10, 0), "n"),
+    (_lib.BfcConfig(256, -1, 4, 0, 0, 1e-10, 0), "L"),
+    (_lib.BfcConfig(256, 4, 4, 7, 0, 1e-10, 0), "precision"),
+    (_lib.BfcConfig(256, 4, 4, 0, 3, 1e-10, 0), "regularization"),
+    (_lib.BfcConfig(256, 4, 4, 0, 0, -1.0, 0), "reg_rel"),
+])
+def test_init_rejects_bad_config(cfg, why):
+    code, msg, h = _init(cfg)
+    assert code == _lib.BFC_EINVAL
+    assert h is None
+    assert msg
+
+
+def test_init_rejects_bad_counts_and_pointers():
+    cfg = _lib.BfcConfig(256, 4, 4, 0, 0, 1e-10, 0)
+    assert _init(cfg, nnz=0)[0] == _lib.BFC_EINVAL
+    assert _init(cfg, rows=0)[0] == _lib.BFC_EINVAL
+    assert _init(cfg, vals=0)[0] == _lib.BFC_EINVAL
+
+
+def test_null_problem_calls():
+    lib = _lib.load()
+    assert lib.bfc_sweep_core(None, 0, None) == _lib.BFC_EINVAL
+    assert lib.bfc_sweep(None, None) == _lib.BFC_EINVAL
+    assert lib.bfc_sync_status(None, None) == _lib.BFC_EINVAL
+    out = (ctypes.c_double * 2)()
+    assert lib.bfc_residual(None, 0, None, None, None, out, None) == _lib.BFC_EINVAL
+    lib.bfc_destroy(None)

@@ -1,0 +1,101 @@
+"""GPU parity at the benchmark's full size (n = 16384, L = 8, r = 6,
+1,835,008 observed entries), in the launch configuration bench.py times.
+
+The oracle cannot redo a whole sweep here in test time, so every core update
+of one sweep is checked on sampled blocks: the oracle recomputes those blocks
+from the GPU's cores before the update, using only the entries that fall in
+them (a block's update depends on nothing else).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2510_17734_amd as bfc
+from workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+SAMPLES = 12
+
+
+@pytest.fixture(scope="module")
+def big():
+    return make_workload("green-line-16384")
+
+
+def _gpu_cores(prob, w):
+    return bfc.unflatten_cores(bfc.get_cores(prob).cpu().numpy(), w.n, w.L, w.r)
+
+
+def _sampled_check(w, precision, sweeps_before=0):
+    cfg = bfc.Config(n=w.n, L=w.L, r=w.r, precision=precision, reg_rel=1e-10)
+    prob = bfc.init_cores(cfg, w.rows, w.cols, w.vals, w.cores0, device=DEV)
+    for _ in range(sweeps_before):
+        bfc.sweep(prob)
+    keys = oracle.block_keys(w.rows, w.cols, w.L, w.c)
+    rng = np.random.default_rng(1 + sweeps_before)
+    worst = {}
+    for p in range(w.L + 2):
+        before = _gpu_cores(prob, w)
+        bfc.sweep_core(prob, p)
+        bfc.sync_status(prob)
+        after = _gpu_cores(prob, w)
+        nb = before[p].shape[0]
+        pick = rng.choice(nb, size=SAMPLES, replace=False)
+        # always include the fullest block
+        counts = np.bincount(keys[p], minlength=nb)
+        pick[0] = int(np.argmax(counts))
+        sel = np.isin(keys[p], pick)
+        ref = oracle.update_core(before, p, w.rows[sel], w.cols[sel], w.vals[sel], w.L,
+                                 reg_rel=1e-10,
+                                 reg_floor=0.0 if precision == "c128" else 2.0 ** -24)
+        if precision == "c128":
+            err = np.max(np.abs(after[p][pick] - ref[p][pick])) / np.max(np.abs(ref[p][pick]))
+            worst[p] = err
+            assert err <= 1e-9, (p, err)
+        else:
+            # block objective of the GPU update against the FP64 optimum: within
+            # 1e-4 relative plus 1e-6 of the blocks' data energy (an FP32 Gram
+            # perturbs the solution by about cond(K) * sqrt(m) * 2^-24)
+            mixed = list(before)
+            mixed[p] = ref[p].copy()
+            f_ref = oracle.objective(mixed, w.rows[sel], w.cols[sel], w.vals[sel], w.L)
+            mixed[p][pick] = after[p][pick]
+            f_gpu = oracle.objective(mixed, w.rows[sel], w.cols[sel], w.vals[sel], w.L)
+            energy = 0.5 * float(np.sum(np.abs(w.vals[sel]) ** 2))
+            worst[p] = (f_gpu - f_ref) / energy
+            assert f_gpu <= f_ref * (1 + 1e-4) + 1e-6 * energy, (p, f_gpu, f_ref, energy)
+        # blocks outside the sample and other cores: untouched by the oracle,
+        # updated by the GPU; other cores must be bit-identical
+        for q in range(w.L + 2):
+            if q != p:
+                assert np.array_equal(after[q], before[q])
+    prob.close()
+    return worst
+
+
+def test_fullsize_sweep_c128_sampled(big):
+    _sampled_check(big, "c128")
+
+
+def test_fullsize_sweep_c64_sampled(big):
+    _sampled_check(big, "c64")
+
+
+def test_fullsize_sweep_c64_sampled_after_eight_sweeps(big):
+    # near the fit the Gram matrices are far worse conditioned than at the start
+    _sampled_check(big, "c64", sweeps_before=8)
+
+
+def test_fullsize_predict_and_residual(big):
+    cfg = bfc.Config(n=big.n, L=big.L, r=big.r, precision="c64", reg_rel=1e-10)
+    prob = bfc.init_cores(cfg, big.rows, big.cols, big.vals, big.cores0, device=DEV)
+    x = bfc.predict_entries(prob, big.test_rows, big.test_cols).cpu().numpy()
+    ref = oracle.predict(big.cores0, big.test_rows, big.test_cols, big.L)
+    assert np.max(np.abs(x - ref)) <= 2e-5 * np.max(np.abs(ref))
+    num, den = bfc.residual(prob, big.rows, big.cols, big.vals)
+    onum, oden = oracle.residual_sq(big.cores0, big.rows, big.cols, big.vals, big.L)
+    assert abs(num - onum) <= 1e-5 * onum
+    assert abs(den - oden) <= 1e-12 * oden
+    prob.close()
