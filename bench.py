@@ -35,37 +35,42 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 
-def inner_gram_flops(stats, nnz, r, L, p):
+def inner_gram_flops(stats, nnz, r):
     """Algorithmic FP work of one inner-core Gram launch: per distinct
     (slice, row|column) run, the Hermitian Kronecker accumulate 4 d (d+1) and
     its right-hand side 8 d (d = r^2); per entry, the Hermitian r x r outer
-    product 4 r (r+1), conj(env) t (8 r) and two cached-environment complex
-    mat-vecs 16 r^2."""
+    product 4 r (r+1) and conj(env) t (8 r)."""
     d = r * r
-    return stats["runs"] * (4 * d * (d + 1) + 8 * d) + nnz * (4 * r * (r + 1) + 8 * r + 16 * r * r)
+    return stats["runs"] * (4 * d * (d + 1) + 8 * d) + nnz * (4 * r * (r + 1) + 8 * r)
 
 
 def outer_flops(nnz, r):
-    """Outer-core update: per entry the Hermitian outer product, conj(a) t and
-    two cached-environment mat-vecs (solves are negligible)."""
-    return nnz * (4 * r * (r + 1) + 8 * r + 16 * r * r)
+    """Outer-core update: per entry the Hermitian outer product and conj(a) t
+    (the r x r solves are negligible)."""
+    return nnz * (4 * r * (r + 1) + 8 * r)
+
+
+def env_flops(env_nodes, r):
+    """Environment trie: one complex r x r mat-vec (8 r^2 flops) per node."""
+    return env_nodes * 8 * r * r
 
 
 def timed_sweeps(bfc, torch, prob, data_dev, steps, warmup):
     rows_d, cols_d, vals_d = data_dev
     for _ in range(warmup):
         bfc.sweep(prob)
-        bfc.residual(prob, rows_d, cols_d, vals_d)
+        bfc.residual_observed(prob)
     bfc.profile_enable(prob, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     last = None
     for _ in range(steps):
         bfc.sweep(prob)
-        last = bfc.residual(prob, rows_d, cols_d, vals_d)
+        last = bfc.residual_observed(prob)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = {k: bfc.profile_read(prob, k) for k in ("outer", "inner_gram", "inner_solve", "residual")}
+    kern = {k: bfc.profile_read(prob, k)
+            for k in ("env", "outer", "inner_gram", "inner_solve", "residual")}
     bfc.profile_enable(prob, False)
     return t1 - t0, kern, last
 
@@ -155,13 +160,13 @@ def main():
     # roofline of the dominant kernel (largest summed event time)
     stats = [bfc.core_stats(prob, p) for p in range(w.L + 2)]
     flops_per_sweep = {
-        "inner_gram": sum(inner_gram_flops(stats[p], w.nnz, w.r, w.L, p) for p in range(1, w.L + 1)),
+        "inner_gram": sum(inner_gram_flops(stats[p], w.nnz, w.r) for p in range(1, w.L + 1)),
         "outer": 2 * outer_flops(w.nnz, w.r),
+        "env": env_flops(bfc.env_nodes(prob), w.r),
     }
-    dom = max(("inner_gram", "outer"), key=lambda k: kern[k][0])
+    dom = max(flops_per_sweep, key=lambda k: kern[k][0])
     dom_ms, dom_launches = kern[dom]
-    launches_per_sweep = w.L if dom == "inner_gram" else 2
-    work = flops_per_sweep[dom] * (dom_launches / launches_per_sweep)
+    work = flops_per_sweep[dom] * args.steps
     achieved = work / (dom_ms * 1e-3) / 1e12
     peak = PEAKS["fp32_TFs"] if args.precision == "c64" else PEAKS["fp64_TFs"]
     roofline = {

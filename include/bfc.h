@@ -159,6 +159,15 @@ bfc_status bfc_residual(const bfc_problem* p, int64_t m, const int32_t* d_rows,
                         const int32_t* d_cols, const void* d_vals, double out_sq[2],
                         void* hip_stream);
 
+/*
+ * The same two norms over the problem's own observed entries (the training
+ * error of eq. (BF_convergence)), from the environments the sweep keeps:
+ * x = (left environment of the last core) . Z^(L+2)[j].  The observed values
+ * are taken in the problem's compute precision.  Synchronizes; reports
+ * pending solve failures like bfc_residual.
+ */
+bfc_status bfc_residual_observed(bfc_problem* p, double out_sq[2], void* hip_stream);
+
 /* Copy the cores out to / in from d_cores (bfc_num_params complex128 values). */
 bfc_status bfc_get_cores(const bfc_problem* p, void* d_cores, void* hip_stream);
 bfc_status bfc_set_cores(bfc_problem* p, const void* d_cores, void* hip_stream);
@@ -188,6 +197,7 @@ bfc_status bfc_solve_counters(bfc_problem* p, int32_t reset, int64_t out[2], voi
 #define BFC_KERNEL_INNER_SOLVE 2  /* inner-core slice solves                              */
 #define BFC_KERNEL_RESIDUAL 3     /* residual norms                                       */
 #define BFC_KERNEL_PREDICT 4      /* entry reconstruction                                 */
+#define BFC_KERNEL_ENV 5          /* environment-trie levels (shared partial products)    */
 bfc_status bfc_profile_enable(bfc_problem* p, int32_t enable);
 bfc_status bfc_profile_read(bfc_problem* p, int32_t kind, double* total_ms, int64_t* launches);
 
@@ -197,9 +207,11 @@ bfc_status bfc_profile_read(bfc_problem* p, int32_t kind, double* total_ms, int6
  * or (slice, column) pairs, holding entries), out[2] = subgroups (runs cut
  * into pieces of at most 8 entries), out[3] = Gram work items (wavefronts),
  * out[4] = 1 if the core groups by row, 0 by column; for an outer core
- * out[1..3] = 0 and out[4] = -1.
+ * out[1..3] = 0 and out[4] = -1.  out[5] / out[6] = distinct right / left
+ * environments of the core that the sweep computes and caches (0 where the
+ * environment is a row of Z^(L+2) / Z^1 or absent).
  */
-bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[5]);
+bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[7]);
 
 /* Release every device allocation of the problem.  NULL is ignored. */
 void bfc_destroy(bfc_problem* p);

@@ -13,6 +13,7 @@ from .api import (  # noqa: F401
     profile_read,
     Problem,
     destroy,
+    env_nodes,
     flatten_cores,
     get_cores,
     init_cores,
@@ -21,6 +22,7 @@ from .api import (  # noqa: F401
     predict_entries,
     relative_error,
     residual,
+    residual_observed,
     set_cores,
     solve_counters,
     sweep,

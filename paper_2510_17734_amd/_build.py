@@ -21,6 +21,8 @@ FLAGS = [
     "-fPIC",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the register-resident solvers unroll O(d^2) loop bodies completely
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -46,9 +46,11 @@ EXPORTS = (
     "bfc_profile_read",
     "bfc_core_stats",
     "bfc_solve_counters",
+    "bfc_residual_observed",
 )
 
-KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4}
+KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
+                "env": 5}
 
 
 class BfcConfig(ctypes.Structure):
@@ -108,6 +110,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_core_stats.restype = i32
     lib.bfc_solve_counters.argtypes = [P, i32, ctypes.POINTER(ctypes.c_int64), vp]
     lib.bfc_solve_counters.restype = i32
+    lib.bfc_residual_observed.argtypes = [P, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_residual_observed.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

@@ -177,6 +177,14 @@ def residual(p: Problem, rows, cols, vals, stream=None):
     return float(out[0]), float(out[1])
 
 
+def residual_observed(p: Problem, stream=None):
+    """bfc_residual_observed: the two norms over the problem's own observed entries."""
+    out = (ctypes.c_double * 2)()
+    _check(_lib.load().bfc_residual_observed(p.handle, out, _stream(stream)),
+           "bfc_residual_observed")
+    return float(out[0]), float(out[1])
+
+
 def relative_error(p: Problem, rows, cols, vals, stream=None) -> float:
     num, den = residual(p, rows, cols, vals, stream)
     return (num / den) ** 0.5 if den > 0 else num ** 0.5
@@ -227,10 +235,17 @@ def profile_read(p: Problem, kind: str):
 
 def core_stats(p: Problem, core: int):
     """bfc_core_stats: blocks, subgroups, work items, grouping of one core."""
-    out = (ctypes.c_int64 * 5)()
+    out = (ctypes.c_int64 * 7)()
     _check(_lib.load().bfc_core_stats(p.handle, int(core), out), "bfc_core_stats")
     return {"blocks": out[0], "runs": out[1], "subgroups": out[2], "items": out[3],
-            "by_row": out[4]}
+            "by_row": out[4], "right_env_nodes": out[5], "left_env_nodes": out[6]}
+
+
+def env_nodes(p: Problem) -> int:
+    """Environment vectors one sweep computes (all cached trie levels)."""
+    L = p.cfg.L
+    return sum(core_stats(p, q)["right_env_nodes"] + core_stats(p, q)["left_env_nodes"]
+               for q in range(L + 2))
 
 
 def solve_counters(p: Problem, reset: bool = False, stream=None):

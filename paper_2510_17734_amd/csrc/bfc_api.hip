@@ -258,6 +258,30 @@ bfc_status bfc_residual(const bfc_problem* p, int64_t m, const int32_t* d_rows,
   return BFC_OK;
 }
 
+bfc_status bfc_residual_observed(bfc_problem* p, double out_sq[2], void* hip_stream) {
+  if (!p || !out_sq) {
+    set_error("bad residual_observed arguments");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* dres = p->red + p->red_len;
+  BFC_TRY(launch_residual_observed(p, dres, st));
+  BFC_HIP_TRY(hipMemcpyAsync(p->red_host, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  int32_t nfail = 0;
+  BFC_HIP_TRY(hipMemcpyAsync(&nfail, p->flags, 4, hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  out_sq[0] = p->red_host[0];
+  out_sq[1] = p->red_host[1];
+  if (nfail) {
+    BFC_HIP_TRY(hipMemsetAsync(p->flags, 0, 4, st));
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+    set_error("a regularized normal-equation matrix was not positive definite (" +
+              std::to_string(nfail) + " blocks kept their values)");
+    return BFC_ENOTSPD;
+  }
+  return BFC_OK;
+}
+
 bfc_status bfc_get_cores(const bfc_problem* p, void* d_cores, void* hip_stream) {
   if (!p || !d_cores) {
     set_error("bad get_cores arguments");
@@ -357,7 +381,7 @@ bfc_status bfc_solve_counters(bfc_problem* p, int32_t reset, int64_t out[2], voi
   return BFC_OK;
 }
 
-bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[5]) {
+bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[7]) {
   if (!p || !out || core < 0 || core > p->L + 1) {
     set_error("bad core_stats arguments");
     return BFC_EINVAL;
@@ -369,6 +393,8 @@ bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[5]) {
   out[2] = inner ? C.nsub : 0;
   out[3] = inner ? C.nitems : 0;
   out[4] = inner ? C.group_by_row : -1;
+  out[5] = core <= p->L - 1 ? p->rlev[core].count : 0;
+  out[6] = core >= 2 ? p->llev[core].count : 0;
   return BFC_OK;
 }
 

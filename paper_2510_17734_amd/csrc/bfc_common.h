@@ -30,9 +30,9 @@ struct Status {
     }                                                                       \
   } while (0)
 
-#define BFC_TRY(expr)                \
+#define BFC_TRY(...)                 \
   do {                               \
-    bfc_status _s = (expr);          \
+    bfc_status _s = (__VA_ARGS__);   \
     if (_s != BFC_OK) return _s;     \
   } while (0)
 
@@ -68,6 +68,10 @@ __host__ __device__ inline void cfma_conj(cx<T>& acc, cx<T> a, cx<T> b) {
 // ---------------------------------------------------------------------------
 // problem state
 // ---------------------------------------------------------------------------
+// Entries per subgroup: runs of one inner slice's row (or column) are cut into
+// pieces of at most this many entries, one lane each in the Gram kernel.
+constexpr int kSubgroup = 8;
+
 struct WorkItem {   // a run of subgroups of one inner-core slice, one wavefront
   int32_t tile, sub0, sub1, pad;
 };
@@ -87,18 +91,37 @@ struct CoreLayout {
   int32_t nitems = 0;
   WorkItem* items = nullptr;
   int32_t* tile_items = nullptr;  // nblocks + 1: item range of each slice
+  // environment node of every sorted entry (nullptr where the environment is
+  // a row of Z^1 or of Z^(L+2) itself)
+  int32_t* lnode = nullptr;
+  int32_t* rnode = nullptr;
+};
+
+// One level of the environment trie.  Right level p (0 <= p < L) holds the
+// distinct right environments of core p, one per (u = ib >> p, column j)
+// present in the observed set, ordered by (u, j); left level p (2 <= p <= L+1)
+// the distinct left environments of core p, one per (w = jb >> (L-p+1), row i),
+// ordered by (w, i).  Each node is one r x r product away from its parent on
+// the adjacent level (or from a row of Z^(L+2) / Z^1 at the ends).
+struct EnvLevel {
+  int32_t count = 0;
+  int32_t* node_a = nullptr;   // u (right) or w (left)
+  int32_t* node_b = nullptr;   // column j (right) or row i (left)
+  int32_t* parent = nullptr;   // node on the adjacent level, or the j / i row
+  void* vec = nullptr;         // count x r complex, compute precision
+  bool valid = false;          // computed from the current cores
 };
 
 // per-kernel timing with HIP events (enabled by bfc_profile_enable)
 enum { KIND_OUTER = 0, KIND_INNER_GRAM = 1, KIND_INNER_SOLVE = 2, KIND_RESIDUAL = 3,
-       KIND_PREDICT = 4, KIND_COUNT = 5 };
+       KIND_PREDICT = 4, KIND_ENV = 5, KIND_COUNT = 6 };
 
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KIND_COUNT];
-  double total_ms[KIND_COUNT] = {0, 0, 0, 0, 0};
-  int64_t launches[KIND_COUNT] = {0, 0, 0, 0, 0};
+  double total_ms[KIND_COUNT] = {0, 0, 0, 0, 0, 0};
+  int64_t launches[KIND_COUNT] = {0, 0, 0, 0, 0, 0};
   hipEvent_t take();
 };
 
@@ -133,6 +156,9 @@ struct Problem {
   double* red_host = nullptr;        // pinned, 2 doubles
   std::vector<void*> allocs;         // everything hipMalloc'd
   int32_t max_items = 0;
+  std::vector<EnvLevel> rlev;        // index p = 0..L-1
+  std::vector<EnvLevel> llev;        // index p = 2..L+1 (0, 1 unused)
+  int64_t env_bytes = 0;
 };
 
 bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes);
@@ -153,5 +179,7 @@ bfc_status launch_residual(const Problem* P, int64_t m, const int32_t* rows, con
 bfc_status launch_convert_cores(Problem* P, const void* src_c128, void* dst_c128, bool to_internal,
                                 hipStream_t st);
 bfc_status launch_random_cores(Problem* P, uint64_t seed, hipStream_t st);
+bfc_status launch_residual_observed(Problem* P, double* out2, hipStream_t st);
+void invalidate_envs(Problem* P);
 
 }  // namespace bfc

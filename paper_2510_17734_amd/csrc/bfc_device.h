@@ -24,6 +24,27 @@ __host__ __device__ inline uint32_t slice_key(uint32_t ib, uint32_t jb, int L, i
   return ((ib >> (q - 1)) << q) | (jb >> (L - q));
 }
 
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with its own L2.  xcd_swizzle maps the hardware block index so that each
+// XCD receives a contiguous range of logical blocks (blocks that share data
+// then share an L2).  A bijection on [0, nblocks).
+__device__ inline int xcd_swizzle(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int per = nblocks / kXcd, rem = nblocks % kXcd;
+  const int x = bid % kXcd, q = bid / kXcd;
+  // XCD x owns logical blocks [start_x, start_x + per + (x < rem))
+  const int start = x * per + (x < rem ? x : rem);
+  return start + q;
+}
+
+// v <- the R-vector at src + idx * R
+template <typename T, int R>
+__device__ inline void load_env(const cx<T>* __restrict__ src, int idx, cx<T> (&v)[R]) {
+  const cx<T>* p = src + (int64_t)idx * R;
+#pragma unroll
+  for (int a = 0; a < R; ++a) v[a] = p[a];
+}
+
 // v <- v * Z   (row vector times an R x R slice)
 template <typename T, int R>
 __device__ inline void vec_mat(cx<T> (&v)[R], const cx<T>* __restrict__ Z) {
@@ -132,32 +153,106 @@ struct Mfma<double> {
   static __device__ inline int out_row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 
-// Hermitian positive definite solve by one wavefront (workgroup of exactly
-// 64 threads, so __syncthreads is a wavefront barrier).  M (d x d, row-major,
-// d <= 64) is overwritten by its lower Cholesky factor.  Returns false if a
-// pivot is not positive (M is then partly overwritten).
-__device__ inline bool wave_cholesky(double2* M, int d, int lane) {
-  for (int k = 0; k < d; ++k) {
-    const double piv = M[k * d + k].x;
+// ---------------------------------------------------------------------------
+// Hermitian positive definite solve by one wavefront (a workgroup of exactly
+// 64 threads, so __syncthreads is a wavefront barrier), d <= 64 unknowns.
+// M is row-major with an odd leading dimension ld (element (i, j) at
+// i*ld + j): a row walk across lanes (stride ld) and a column walk
+// (consecutive j) both touch distinct LDS banks.  Lane i owns row i.
+// ---------------------------------------------------------------------------
+
+// Uniform-lane broadcast of a double (lane index in a scalar register).
+__device__ inline double bcast_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Blocked factorization, panel width kNb: per panel the kNb x kNb diagonal
+// block is factored redundantly in every lane's registers, the rows below
+// solve for their panel entries, and the trailing update subtracts a rank-kNb
+// product.  panel (d x kNb values of LDS) holds the panel for the trailing
+// reads, an array the row updates never write.
+constexpr int kNb = 4;
+
+// Factor the nb x nb lower block at (k0, k0) of M into D (registers).
+__device__ __attribute__((always_inline)) inline bool diag_block_factor(const double2* M, int ld,
+                                                                         int k0, int nb,
+                                                                         double2 (&D)[kNb][kNb]) {
+#pragma unroll
+  for (int a = 0; a < kNb; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b)
+      D[a][b] = (a < nb) ? M[(k0 + a) * ld + k0 + b] : make_double2(a == b ? 1.0 : 0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < kNb; ++k) {
+    const double piv = D[k][k].x;
     if (!(piv > 0.0)) return false;
-    const double lkk = sqrt(piv);
-    const double inv = 1.0 / lkk;
-    __syncthreads();
-    if (lane > k && lane < d) {
-      double2 v = M[lane * d + k];
-      M[lane * d + k] = make_double2(v.x * inv, v.y * inv);
+    const double lkk = sqrt(piv), inv = 1.0 / lkk;
+    D[k][k] = make_double2(lkk, 0.0);
+#pragma unroll
+    for (int i = k + 1; i < kNb; ++i) {
+      D[i][k].x *= inv;
+      D[i][k].y *= inv;
     }
-    if (lane == k) M[k * d + k] = make_double2(lkk, 0.0);
+#pragma unroll
+    for (int j = k + 1; j < kNb; ++j)
+#pragma unroll
+      for (int i = j; i < kNb; ++i) {
+        D[i][j].x -= D[i][k].x * D[j][k].x + D[i][k].y * D[j][k].y;
+        D[i][j].y -= D[i][k].y * D[j][k].x - D[i][k].x * D[j][k].y;
+      }
+  }
+  return true;
+}
+
+// In-place lower Cholesky factor of the d x d matrix M.  Returns false if a
+// pivot is not positive (the result is the same in every lane).
+__device__ inline bool lds_cholesky(double2* M, int d, int ld, double2* panel, int lane) {
+  for (int k0 = 0; k0 < d; k0 += kNb) {
+    const int nb = d - k0 < kNb ? d - k0 : kNb;
+    double2 D[kNb][kNb];
+    if (!diag_block_factor(M, ld, k0, nb, D)) return false;
+    double2 Li[kNb];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) Li[q] = make_double2(0.0, 0.0);
+    if (lane >= k0 + nb && lane < d) {
+      // L_i L_D^H = a_i, solved by forward substitution over the panel
+#pragma unroll
+      for (int q = 0; q < kNb; ++q) {
+        if (q >= nb) break;
+        double2 v = M[lane * ld + k0 + q];
+#pragma unroll
+        for (int p = 0; p < q; ++p) {  // v -= L_i[p] conj(L_D[q][p])
+          v.x -= Li[p].x * D[q][p].x + Li[p].y * D[q][p].y;
+          v.y -= Li[p].y * D[q][p].x - Li[p].x * D[q][p].y;
+        }
+        const double inv = 1.0 / D[q][q].x;
+        Li[q] = make_double2(v.x * inv, v.y * inv);
+        M[lane * ld + k0 + q] = Li[q];
+        panel[lane * kNb + q] = Li[q];
+      }
+    } else if (lane >= k0 && lane < k0 + nb) {
+      const int a = lane - k0;
+#pragma unroll
+      for (int q = 0; q < kNb; ++q)
+#pragma unroll
+        for (int r = 0; r < kNb; ++r)
+          if (r == a && q <= r) M[lane * ld + k0 + q] = D[r][q];
+    }
     __syncthreads();
-    if (lane > k && lane < d) {
-      const double2 lik = M[lane * d + k];
-      for (int j = k + 1; j <= lane; ++j) {
-        const double2 ljk = M[j * d + k];
-        double2 m = M[lane * d + j];
-        // m -= lik * conj(ljk)
-        m.x -= lik.x * ljk.x + lik.y * ljk.y;
-        m.y -= lik.y * ljk.x - lik.x * ljk.y;
-        M[lane * d + j] = m;
+    if (lane >= k0 + nb && lane < d) {
+      double2* row = M + lane * ld;
+      for (int j = k0 + nb; j <= lane; ++j) {
+        const double2* pj = panel + j * kNb;  // same address in every lane
+        double2 m = row[j];
+#pragma unroll
+        for (int q = 0; q < kNb; ++q) {
+          const double2 c = pj[q];
+          m.x -= Li[q].x * c.x + Li[q].y * c.y;  // m -= L_i[q] conj(L_j[q])
+          m.y -= Li[q].y * c.x - Li[q].x * c.y;
+        }
+        row[j] = m;
       }
     }
     __syncthreads();
@@ -165,38 +260,155 @@ __device__ inline bool wave_cholesky(double2* M, int d, int lane) {
   return true;
 }
 
-// Solve (L L^H) s = b with the factor from wave_cholesky; b (LDS, length d)
-// is overwritten by s.
-__device__ inline void wave_chol_solve(const double2* M, double2* b, int d, int lane) {
-  for (int k = 0; k < d; ++k) {
-    __syncthreads();
-    const double inv = 1.0 / M[k * d + k].x;
-    const double2 yk = make_double2(b[k].x * inv, b[k].y * inv);
-    __syncthreads();
-    if (lane == k) b[k] = yk;
-    if (lane > k && lane < d) {
-      const double2 lik = M[lane * d + k];
-      double2 v = b[lane];
-      v.x -= lik.x * yk.x - lik.y * yk.y;
-      v.y -= lik.x * yk.y + lik.y * yk.x;
-      b[lane] = v;
+// Solve L L^H s = b with the factor of lds_cholesky.  Lane i holds b_i in a
+// register and ends with s_i; lanes >= d carry nothing of use.  Blocked by
+// kNb columns; no LDS writes and no barriers: the block's running values are
+// broadcast with readlane and its triangle is read by every lane.
+__device__ inline void lds_chol_solve(const double2* M, int d, int ld, double2& b, int lane) {
+  const int li = lane < d ? lane : 0;
+  for (int k0 = 0; k0 < d; k0 += kNb) {  // L y = b
+    const int nb = d - k0 < kNb ? d - k0 : kNb;
+    double2 y[kNb];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) {
+      y[q] = make_double2(0.0, 0.0);
+      if (q >= nb) continue;
+      double2 v = make_double2(bcast_d(b.x, k0 + q), bcast_d(b.y, k0 + q));
+#pragma unroll
+      for (int p = 0; p < q; ++p) {
+        const double2 l = M[(k0 + q) * ld + k0 + p];
+        v.x -= l.x * y[p].x - l.y * y[p].y;
+        v.y -= l.x * y[p].y + l.y * y[p].x;
+      }
+      const double inv = 1.0 / M[(k0 + q) * ld + k0 + q].x;
+      y[q] = make_double2(v.x * inv, v.y * inv);
+      if (lane == k0 + q) b = y[q];
+    }
+    if (lane >= k0 + nb && lane < d) {
+#pragma unroll
+      for (int q = 0; q < kNb; ++q) {
+        if (q >= nb) break;
+        const double2 l = M[li * ld + k0 + q];
+        b.x -= l.x * y[q].x - l.y * y[q].y;
+        b.y -= l.x * y[q].y + l.y * y[q].x;
+      }
     }
   }
-  for (int k = d - 1; k >= 0; --k) {
-    __syncthreads();
-    const double inv = 1.0 / M[k * d + k].x;
-    const double2 sk = make_double2(b[k].x * inv, b[k].y * inv);
-    __syncthreads();
-    if (lane == k) b[k] = sk;
-    if (lane < k) {
-      const double2 lki = M[k * d + lane];  // (L^H)[lane][k] = conj(L[k][lane])
-      double2 v = b[lane];
-      v.x -= lki.x * sk.x + lki.y * sk.y;
-      v.y -= lki.x * sk.y - lki.y * sk.x;
-      b[lane] = v;
+  const int last = ((d - 1) / kNb) * kNb;
+  for (int k0 = last; k0 >= 0; k0 -= kNb) {  // L^H s = y
+    const int nb = d - k0 < kNb ? d - k0 : kNb;
+    double2 x[kNb];
+#pragma unroll
+    for (int q = kNb - 1; q >= 0; --q) {
+      x[q] = make_double2(0.0, 0.0);
+      if (q >= nb) continue;
+      double2 v = make_double2(bcast_d(b.x, k0 + q), bcast_d(b.y, k0 + q));
+#pragma unroll
+      for (int p = q + 1; p < kNb; ++p) {  // v -= conj(L[k0+p][k0+q]) s_p
+        if (p >= nb) break;
+        const double2 l = M[(k0 + p) * ld + k0 + q];
+        v.x -= l.x * x[p].x + l.y * x[p].y;
+        v.y -= l.x * x[p].y - l.y * x[p].x;
+      }
+      const double inv = 1.0 / M[(k0 + q) * ld + k0 + q].x;
+      x[q] = make_double2(v.x * inv, v.y * inv);
+      if (lane == k0 + q) b = x[q];
+    }
+    if (lane < k0) {
+#pragma unroll
+      for (int q = 0; q < kNb; ++q) {
+        if (q >= nb) break;
+        const double2 l = M[(k0 + q) * ld + li];  // conj(L[k0+q][lane]) s_q
+        b.x -= l.x * x[q].x + l.y * x[q].y;
+        b.y -= l.x * x[q].y - l.y * x[q].x;
+      }
     }
   }
-  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Sums over one DPP row (16 lanes): butterfly with quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror and row_mirror.  Every lane of the row
+// ends with the same, identically ordered sum.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float row16_sum(float v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  return v;
+}
+__device__ inline double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Serial Hermitian solve in registers (one lane), small R.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __attribute__((always_inline)) inline bool serial_cholesky(double2 (&M)[R][R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const double piv = M[k][k].x;
+    if (!(piv > 0.0)) return false;
+    const double lkk = sqrt(piv), inv = 1.0 / lkk;
+    M[k][k] = make_double2(lkk, 0.0);
+#pragma unroll
+    for (int i = k + 1; i < R; ++i) {
+      M[i][k].x *= inv;
+      M[i][k].y *= inv;
+    }
+#pragma unroll
+    for (int j = k + 1; j < R; ++j)
+#pragma unroll
+      for (int i = j; i < R; ++i) {
+        M[i][j].x -= M[i][k].x * M[j][k].x + M[i][k].y * M[j][k].y;
+        M[i][j].y -= M[i][k].y * M[j][k].x - M[i][k].x * M[j][k].y;
+      }
+  }
+  return true;
+}
+
+template <int R>
+__device__ __attribute__((always_inline)) inline void serial_chol_solve(const double2 (&M)[R][R],
+                                                                        double2 (&b)[R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const double inv = 1.0 / M[k][k].x;
+    b[k].x *= inv;
+    b[k].y *= inv;
+#pragma unroll
+    for (int i = k + 1; i < R; ++i) {
+      b[i].x -= M[i][k].x * b[k].x - M[i][k].y * b[k].y;
+      b[i].y -= M[i][k].x * b[k].y + M[i][k].y * b[k].x;
+    }
+  }
+#pragma unroll
+  for (int k = R - 1; k >= 0; --k) {
+    const double inv = 1.0 / M[k][k].x;
+    b[k].x *= inv;
+    b[k].y *= inv;
+#pragma unroll
+    for (int i = 0; i < k; ++i) {  // b_i -= conj(L[k][i]) s_k
+      b[i].x -= M[k][i].x * b[k].x + M[k][i].y * b[k].y;
+      b[i].y -= M[k][i].x * b[k].y - M[k][i].y * b[k].x;
+    }
+  }
 }
 
 // Deterministic sum over the 64 lanes of a wavefront (every lane gets the

@@ -20,8 +20,6 @@ namespace bfc {
 
 namespace {
 
-constexpr int kSubgroup = 8;
-
 __global__ void validate_kernel(const int32_t* rows, const int32_t* cols, const double2* vals,
                                 int64_t nnz, int64_t n, int32_t* flag) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -127,6 +125,50 @@ __global__ void tile_subs_kernel(const int32_t* blk_off, const int32_t* sub_id, 
   tile_sub[b] = (k < nnz) ? sub_id[k] : nsub;
 }
 
+// Environment-trie levels: right level p keys entries by (ib >> p, j), left
+// level p by (jb >> (L-p+1), i); equal keys share one environment vector.
+__global__ void level_keys_kernel(const int32_t* rows, const int32_t* cols, int64_t nnz, int c,
+                                  int L, int p, int right, uint32_t n, uint32_t* keys,
+                                  int32_t* idx) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const uint32_t i = (uint32_t)rows[e], j = (uint32_t)cols[e];
+  uint32_t key;
+  if (right)
+    key = ((i / c) >> p) * n + j;
+  else
+    key = ((j / c) >> (L - p + 1)) * n + i;
+  keys[e] = key;
+  idx[e] = (int32_t)e;
+}
+
+// head/hscan: run heads of the sorted keys and their exclusive scan
+__global__ void node_table_kernel(const uint32_t* skeys, const int32_t* idx, const int32_t* head,
+                                  const int32_t* hscan, int64_t nnz, uint32_t n, int32_t* node_a,
+                                  int32_t* node_b, int32_t* ent_node) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const int32_t id = hscan[k] + head[k] - 1;
+  if (head[k]) {
+    node_a[id] = (int32_t)(skeys[k] / n);
+    node_b[id] = (int32_t)(skeys[k] % n);
+  }
+  ent_node[idx[k]] = id;
+}
+
+// every entry of a node names the same parent, so concurrent writes agree
+__global__ void parent_kernel(const int32_t* ent_child, const int32_t* ent_parent, int64_t nnz,
+                              int32_t* parent) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) parent[ent_child[e]] = ent_parent[e];
+}
+
+__global__ void gather_i32_kernel(const int32_t* idx, const int32_t* src, int64_t nnz,
+                                  int32_t* dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) dst[k] = src[idx[k]];
+}
+
 inline unsigned grid_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 int bits_for(uint64_t maxval) {
@@ -199,6 +241,55 @@ bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols
 
   const int64_t n = P->n;
   const int c = P->c;
+  if (((uint64_t)n << L) > 0xFFFFFFFFull) {
+    set_error("bfc_init_cores: n * 2^L must stay below 2^32");
+    return BFC_EINVAL;
+  }
+
+  // environment-trie levels: per-entry node ids (input order), node tables
+  std::vector<int32_t*> ent_r(L + 2, nullptr), ent_l(L + 2, nullptr);
+  P->rlev.assign(L, EnvLevel());
+  P->llev.assign(L + 2, EnvLevel());
+  auto build_level = [&](int p, bool right, EnvLevel& E, int32_t*& ent) -> bfc_status {
+    BFC_HIP_TRY(S.get((void**)&ent, nnz * 4));
+    const uint64_t span = right ? ((uint64_t)1 << (L - p)) : ((uint64_t)1 << (p - 1));
+    level_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(d_rows, d_cols, nnz, c, L, p, right ? 1 : 0,
+                                                     (uint32_t)n, keys, idx);
+    BFC_HIP_TRY(hipGetLastError());
+    BFC_HIP_TRY(radix_sort_pairs(keys, idx, nnz, bits_for(span * n - 1), rscr, st));
+    run_heads_kernel<<<grid_for(nnz), 256, 0, st>>>(keys, nnz, head, tmp);
+    BFC_HIP_TRY(exclusive_scan_i32(tmp, nnz, scan_scr, st));
+    int32_t last[2];
+    BFC_HIP_TRY(hipMemcpyAsync(&last[0], tmp + nnz - 1, 4, hipMemcpyDeviceToHost, st));
+    BFC_HIP_TRY(hipMemcpyAsync(&last[1], head + nnz - 1, 4, hipMemcpyDeviceToHost, st));
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+    E.count = last[0] + last[1];
+    BFC_TRY(dev_alloc(P, (void**)&E.node_a, (size_t)E.count * 4));
+    BFC_TRY(dev_alloc(P, (void**)&E.node_b, (size_t)E.count * 4));
+    BFC_TRY(dev_alloc(P, (void**)&E.parent, (size_t)E.count * 4));
+    BFC_TRY(dev_alloc(P, &E.vec, (size_t)E.count * P->r * P->elem));
+    P->env_bytes += (int64_t)E.count * (12 + P->r * (int64_t)P->elem);
+    node_table_kernel<<<grid_for(nnz), 256, 0, st>>>(keys, idx, head, tmp, nnz, (uint32_t)n,
+                                                     E.node_a, E.node_b, ent);
+    BFC_HIP_TRY(hipGetLastError());
+    return BFC_OK;
+  };
+  for (int p = L - 1; p >= 0; --p) BFC_TRY(build_level(p, true, P->rlev[p], ent_r[p]));
+  for (int p = 2; p <= L + 1; ++p) BFC_TRY(build_level(p, false, P->llev[p], ent_l[p]));
+  // parents: right level p -> right level p+1 (level L-1 points at the column
+  // j itself); left level p -> left level p-1 (level 2 points at the row i)
+  for (int p = 0; p + 1 <= L - 1; ++p)
+    parent_kernel<<<grid_for(nnz), 256, 0, st>>>(ent_r[p], ent_r[p + 1], nnz, P->rlev[p].parent);
+  if (L >= 1)
+    BFC_HIP_TRY(hipMemcpyAsync(P->rlev[L - 1].parent, P->rlev[L - 1].node_b,
+                               (size_t)P->rlev[L - 1].count * 4, hipMemcpyDeviceToDevice, st));
+  for (int p = 3; p <= L + 1; ++p)
+    parent_kernel<<<grid_for(nnz), 256, 0, st>>>(ent_l[p], ent_l[p - 1], nnz, P->llev[p].parent);
+  if (L >= 1)
+    BFC_HIP_TRY(hipMemcpyAsync(P->llev[2].parent, P->llev[2].node_b,
+                               (size_t)P->llev[2].count * 4, hipMemcpyDeviceToDevice, st));
+  BFC_HIP_TRY(hipGetLastError());
+
   P->lay.assign(L + 2, CoreLayout());
   int32_t max_items = 0;
   for (int p = 0; p <= L + 1; ++p) {
@@ -236,6 +327,17 @@ bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols
           (cx<float>*)C.vals);
     BFC_HIP_TRY(hipGetLastError());
     block_offsets_kernel<<<grid_for(nnz), 256, 0, st>>>(keys, nnz, ext, C.nblocks, C.blk_off);
+    BFC_HIP_TRY(hipGetLastError());
+    // environment nodes of the sorted entries: right level p (p < L) and
+    // left level p (p >= 2)
+    if (p <= L - 1) {
+      BFC_TRY(dev_alloc(P, (void**)&C.rnode, nnz * 4));
+      gather_i32_kernel<<<grid_for(nnz), 256, 0, st>>>(idx, ent_r[p], nnz, C.rnode);
+    }
+    if (p >= 2) {
+      BFC_TRY(dev_alloc(P, (void**)&C.lnode, nnz * 4));
+      gather_i32_kernel<<<grid_for(nnz), 256, 0, st>>>(idx, ent_l[p], nnz, C.lnode);
+    }
     BFC_HIP_TRY(hipGetLastError());
     if (!inner) continue;
 

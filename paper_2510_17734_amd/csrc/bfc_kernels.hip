@@ -18,6 +18,8 @@
 // Work items (runs of subgroups of one slice) write partial products; a
 // second kernel sums them per slice in a fixed order, forms the Hermitian
 // system in FP64 and solves it with one wavefront.
+#include <type_traits>
+
 #include "bfc_device.h"
 
 namespace bfc {
@@ -142,71 +144,67 @@ __device__ inline double2 inner_h(const double* S, int W, int row) {
 }
 
 // ---------------------------------------------------------------------------
-// outer cores: one wavefront (workgroup of 64) per fiber, fused solve
+// outer cores: 16 lanes (one DPP row) per fiber, fused serial solve
 // ---------------------------------------------------------------------------
+constexpr int kOuterThreads = 256;
+
 template <typename T, int R>
-__global__ __launch_bounds__(64) void outer_update_kernel(
-    cx<T>* cores, int64_t n, int L, int c, int last, const int32_t* rows, const int32_t* cols,
-    const cx<T>* vals, const int32_t* blk_off, int nblocks, double reg_rel, double reg_floor,
-    int prox, int32_t* flags) {
+__global__ __launch_bounds__(kOuterThreads) void outer_update_kernel(
+    cx<T>* fibers, const cx<T>* env, const int32_t* env_idx, const cx<T>* vals,
+    const int32_t* blk_off, int nblocks, double reg_rel, double reg_floor, int prox,
+    int32_t* flags) {
   constexpr int D = R * R;
-  __shared__ double2 M[R * R];
-  __shared__ double2 rhs[R];
-  __shared__ double2 sol[R];
-  __shared__ double Ssh[D + 2 * R];
-  const int lane = threadIdx.x;
-  const int b = blockIdx.x;
-  const int e0 = blk_off[b], e1 = blk_off[b + 1];
-  if (e0 == e1) return;  // no observed entry: keep the fiber
+  const int sub = threadIdx.x & 15;
+  const int b = (xcd_swizzle(blockIdx.x, gridDim.x) * kOuterThreads + threadIdx.x) >> 4;
+  int e0 = 0, e1 = 0;
+  if (b < nblocks) {
+    e0 = blk_off[b];
+    e1 = blk_off[b + 1];
+  }
   T acc[D];
   T hx[R], hy[R];
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = T(0);
 #pragma unroll
   for (int k = 0; k < R; ++k) hx[k] = hy[k] = T(0);
-  for (int e = e0 + lane; e < e1; e += 64) {
-    const int i = rows[e], j = cols[e];
-    const uint32_t ib = (uint32_t)i / (uint32_t)c, jb = (uint32_t)j / (uint32_t)c;
-    const cx<T> t = vals[e];
-    cx<T> a[R];
-    if (last)
-      left_chain<T, R>(cores, n, L, L + 1, i, ib, jb, a);
-    else
-      right_chain<T, R>(cores, n, L, 0, j, ib, jb, a);
-    herm_acc<T, R>(acc, a);
+  for (int base = e0 + sub; base < e1; base += 16 * 4) {
+    int id[4];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      cx<T> h = {hx[k], hy[k]};
-      cfma_conj(h, a[k], t);
-      hx[k] = h.x;
-      hy[k] = h.y;
+    for (int q = 0; q < 4; ++q) id[q] = (base + 16 * q < e1) ? env_idx[base + 16 * q] : -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (id[q] < 0) continue;
+      const cx<T> t = vals[base + 16 * q];
+      cx<T> a[R];
+      load_env<T, R>(env, id[q], a);
+      herm_acc<T, R>(acc, a);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        cx<T> h = {hx[k], hy[k]};
+        cfma_conj(h, a[k], t);
+        hx[k] = h.x;
+        hy[k] = h.y;
+      }
     }
   }
+  // every lane of the wavefront takes part in the row reductions
 #pragma unroll
-  for (int k = 0; k < D; ++k) acc[k] = wave_sum(acc[k]);
+  for (int k = 0; k < D; ++k) acc[k] = row16_sum(acc[k]);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    hx[k] = wave_sum(hx[k]);
-    hy[k] = wave_sum(hy[k]);
+    hx[k] = row16_sum(hx[k]);
+    hy[k] = row16_sum(hy[k]);
   }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) Ssh[k] = (double)acc[k];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      Ssh[D + k] = (double)hx[k];
-      Ssh[D + R + k] = (double)hy[k];
-    }
-  }
-  __syncthreads();
+  if (sub != 0 || b >= nblocks || e0 == e1) return;  // empty fiber: keep it
   // K[a][a2] from the real coordinates; trace; regularization ladder
   double tr = 0.0;
 #pragma unroll
-  for (int a = 0; a < R; ++a) tr += Ssh[a * R + a];
+  for (int a = 0; a < R; ++a) tr += (double)acc[a * R + a];
   const double tau = tr / R;
   const double unit = fmax(reg_floor, 0x1p-53);
   double lam = fmax(reg_rel, R * reg_floor) * tau;
-  cx<T>* fiber = cores + (last ? last_off(n, L, R) : 0) + (int64_t)b * R;
+  cx<T>* fiber = fibers + (int64_t)b * R;
+  double2 M[R][R];
   bool ok = false;
   int attempt = 0;
   for (; attempt < 4; ++attempt) {
@@ -214,55 +212,50 @@ __global__ __launch_bounds__(64) void outer_update_kernel(
       if (!(lam > 0.0)) break;
       lam = fmax(100.0 * lam, R * unit * tau);
     }
-    __syncthreads();
-    if (lane < R * R) {
-      const int a = lane / R, a2 = lane % R;
-      int re, im, sg;
-      herm_coord(a, a2, R, re, im, sg);
-      double2 v = make_double2(Ssh[re], im >= 0 ? sg * Ssh[im] : 0.0);
-      if (a == a2) v.x += lam;
-      M[lane] = v;
-    }
-    if (lane < R) {
-      const cx<T> old = fiber[lane];
-      double2 h = make_double2(Ssh[D + lane], Ssh[D + R + lane]);
-      if (prox) {
-        h.x += lam * (double)old.x;
-        h.y += lam * (double)old.y;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        int re, im, sg;
+        herm_coord(i, j, R, re, im, sg);
+        M[i][j] = make_double2((double)acc[re], im >= 0 ? sg * (double)acc[im] : 0.0);
+        if (i == j) M[i][j].x += lam;
       }
-      rhs[lane] = h;
-      sol[lane] = h;
-    }
-    __syncthreads();
-    ok = wave_cholesky(M, R, lane);
+    ok = serial_cholesky<R>(M);
     if (ok) break;
   }
   if (!ok) {
-    if (lane == 0) atomicAdd(flags, 1);
+    atomicAdd(flags, 1);
     return;
   }
-  if (attempt > 0 && lane == 0) atomicAdd(flags + 1, 1);
-  wave_chol_solve(M, sol, R, lane);
-  // one refinement step against the assembled FP64 system
-  if (lane < R) {
-    double2 res = rhs[lane];
-    for (int k = 0; k < R; ++k) {
-      int re, im, sg;
-      herm_coord(lane, k, R, re, im, sg);
-      double2 m = make_double2(Ssh[re], im >= 0 ? sg * Ssh[im] : 0.0);
-      if (k == lane) m.x += lam;
-      const double2 s = sol[k];
-      res.x -= m.x * s.x - m.y * s.y;
-      res.y -= m.x * s.y + m.y * s.x;
+  if (attempt > 0) atomicAdd(flags + 1, 1);
+  double2 rhs[R], sol[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    rhs[k] = make_double2((double)hx[k], (double)hy[k]);
+    if (prox) {
+      rhs[k].x += lam * (double)fiber[k].x;
+      rhs[k].y += lam * (double)fiber[k].y;
     }
-    rhs[lane] = res;
+    sol[k] = rhs[k];
   }
-  __syncthreads();
-  wave_chol_solve(M, rhs, R, lane);
-  if (lane < R) {
-    const double2 s = sol[lane], d = rhs[lane];
-    fiber[lane] = {T(s.x + d.x), T(s.y + d.y)};
+  serial_chol_solve<R>(M, sol);
+  // one refinement step against the assembled FP64 system
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      int re, im, sg;
+      herm_coord(i, j, R, re, im, sg);
+      double mx = (double)acc[re], my = im >= 0 ? sg * (double)acc[im] : 0.0;
+      if (i == j) mx += lam;
+      rhs[i].x -= mx * sol[j].x - my * sol[j].y;
+      rhs[i].y -= mx * sol[j].y + my * sol[j].x;
+    }
   }
+  serial_chol_solve<R>(M, rhs);
+#pragma unroll
+  for (int k = 0; k < R; ++k) fiber[k] = {T(sol[k].x + rhs[k].x), T(sol[k].y + rhs[k].y)};
 }
 
 // ---------------------------------------------------------------------------
@@ -279,14 +272,15 @@ struct InnerGeom {
 
 template <typename T, int R, int BYROW>
 __global__ __launch_bounds__(64) void inner_gram_kernel(
-    const cx<T>* cores, int64_t n, int L, int c, int p, const int32_t* rows, const int32_t* cols,
+    const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv, const int32_t* ridx,
     const cx<T>* vals, const int32_t* sub_off, const WorkItem* items, T* partials) {
   typedef InnerGeom<R> G;
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[64 * G::LDW];
   __shared__ T Bs[64 * G::LDW];
   const int lane = threadIdx.x;
-  const WorkItem it = items[blockIdx.x];
+  const int item = xcd_swizzle(blockIdx.x, gridDim.x);
+  const WorkItem it = items[item];
   acc_t acc[G::NB][G::NB];
 #pragma unroll
   for (int x = 0; x < G::NB; ++x)
@@ -304,8 +298,6 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
     }
     if (s < it.sub1) {
       const int e0 = sub_off[s], e1 = sub_off[s + 1];
-      const int i0 = rows[e0], j0 = cols[e0];
-      const uint32_t ib0 = (uint32_t)i0 / (uint32_t)c, jb0 = (uint32_t)j0 / (uint32_t)c;
       T sum[G::D];
       T yx[R], yy[R];
 #pragma unroll
@@ -313,28 +305,39 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
 #pragma unroll
       for (int k = 0; k < R; ++k) yx[k] = yy[k] = T(0);
       cx<T> shared_env[R];
-      if (BYROW) {
-        // one row: left environment shared, right environment per entry
-        left_chain<T, R>(cores, n, L, p, i0, ib0, jb0, shared_env);
-        for (int e = e0; e < e1; ++e) {
-          const int j = cols[e];
-          const uint32_t jb = (uint32_t)j / (uint32_t)c;
-          const cx<T> t = vals[e];
-          cx<T> rho[R];
-          right_chain<T, R>(cores, n, L, p, j, ib0, jb, rho);
-          herm_acc<T, R>(sum, rho);
+      // the subgroup shares its row (left environment) or its column (right)
+      if (BYROW)
+        load_env<T, R>(lenv, lidx[e0], shared_env);
+      else
+        load_env<T, R>(renv, ridx[e0], shared_env);
+      // a subgroup holds at most kSubgroup entries: issue every index load,
+      // then every vector load, then compute
+      const int32_t* eidx = BYROW ? ridx : lidx;
+      const cx<T>* esrc = BYROW ? renv : lenv;
+      int id[kSubgroup];
 #pragma unroll
-          for (int k = 0; k < R; ++k) {
-            cx<T> h = {yx[k], yy[k]};
-            cfma_conj(h, rho[k], t);
-            yx[k] = h.x;
-            yy[k] = h.y;
-          }
+      for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kSubgroup; ++q) {
+        if (id[q] < 0) continue;
+        const cx<T> t = vals[e0 + q];
+        cx<T> v[R];
+        load_env<T, R>(esrc, id[q], v);
+        herm_acc<T, R>(sum, v);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          cx<T> h = {yx[k], yy[k]};
+          cfma_conj(h, v[k], t);
+          yx[k] = h.x;
+          yy[k] = h.y;
         }
-        T tmp[G::D];
+      }
+      T tmp[G::D];
 #pragma unroll
-        for (int k = 0; k < G::D; ++k) tmp[k] = T(0);
-        herm_acc<T, R>(tmp, shared_env);
+      for (int k = 0; k < G::D; ++k) tmp[k] = T(0);
+      herm_acc<T, R>(tmp, shared_env);
+      if (BYROW) {
+        // A = [Rl | Re l | Im l], B = [sum Rrho | Re y | Im y], y = sum conj(rho) t
 #pragma unroll
         for (int k = 0; k < G::D; ++k) {
           arow[k] = tmp[k];
@@ -348,34 +351,14 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
           brow[G::D + R + k] = yy[k];
         }
       } else {
-        // one column: right environment shared, left environment per entry
-        right_chain<T, R>(cores, n, L, p, j0, ib0, jb0, shared_env);
-        for (int e = e0; e < e1; ++e) {
-          const int i = rows[e];
-          const uint32_t ib = (uint32_t)i / (uint32_t)c;
-          const cx<T> t = vals[e];
-          cx<T> lft[R];
-          left_chain<T, R>(cores, n, L, p, i, ib, jb0, lft);
-          herm_acc<T, R>(sum, lft);
-#pragma unroll
-          for (int k = 0; k < R; ++k) {
-            cx<T> h = {yx[k], yy[k]};
-            cfma_conj(h, lft[k], t);
-            yx[k] = h.x;
-            yy[k] = h.y;
-          }
-        }
-        T tmp[G::D];
-#pragma unroll
-        for (int k = 0; k < G::D; ++k) tmp[k] = T(0);
-        herm_acc<T, R>(tmp, shared_env);
+        // A = [sum Rl | Re w | -Im w], B = [Rrho | Re rho | -Im rho],
+        // w = sum conj(l) t: the imaginary parts are negated so that the
+        // right-hand side reads the same way as in the row case
 #pragma unroll
         for (int k = 0; k < G::D; ++k) {
           arow[k] = sum[k];
           brow[k] = tmp[k];
         }
-        // w = sum conj(l) t on the A side, rho on the B side, imaginary parts
-        // negated so that the right-hand side reads like the row case
 #pragma unroll
         for (int k = 0; k < R; ++k) {
           arow[G::D + k] = yx[k];
@@ -402,7 +385,7 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
     }
     __syncthreads();
   }
-  T* out = partials + (int64_t)blockIdx.x * G::WP * G::WP;
+  T* out = partials + (int64_t)item * G::WP * G::WP;
 #pragma unroll
   for (int x = 0; x < G::NB; ++x)
 #pragma unroll
@@ -418,34 +401,101 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
 // ---------------------------------------------------------------------------
 // inner cores: per-slice sum of partials, FP64 Hermitian solve (one wavefront)
 // ---------------------------------------------------------------------------
+// One wavefront per slice: sum the work items' partial products in a fixed
+// order, assemble the Hermitian FP64 system (odd leading
+// dimension, row-major) and solve it with the regularization ladder and one refinement
+// step.  LDS: the real partial sum S is only needed to assemble K and h, so
+// the factor M reuses its space.
+template <int R>
+struct SolveGeom {
+  static constexpr int D = R * R;
+  static constexpr int WP = InnerGeom<R>::WP;
+  static constexpr int LD = (D % 2) ? D : D + 1;
+  static constexpr int K_BYTES = D * LD * 16;
+  static constexpr int S_BYTES = WP * WP * 8;
+  static constexpr int M_BYTES = (K_BYTES > S_BYTES ? K_BYTES : S_BYTES);
+};
+
 template <typename T, int R>
 __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T* partials,
                                                          const int32_t* tile_items,
                                                          double reg_rel, double reg_floor,
                                                          int prox, int32_t* flags) {
-  typedef InnerGeom<R> G;
-  constexpr int D = G::D;
-  constexpr int WP = G::WP;
-  __shared__ double S[WP * WP];
-  __shared__ double2 M[D * D];
-  __shared__ double2 rhs[D];
-  __shared__ double2 sol[D];
+  typedef SolveGeom<R> G;
+  constexpr int D = G::D, WP = G::WP, LD = G::LD;
+  __shared__ double2 K[D * LD];
+  __shared__ __attribute__((aligned(16))) unsigned char mbuf[G::M_BYTES];
+  __shared__ double2 panel[D * kNb];
+  double* S = (double*)mbuf;
+  double2* M = (double2*)mbuf;
   const int lane = threadIdx.x;
   const int tile = blockIdx.x;
   const int it0 = tile_items[tile], it1 = tile_items[tile + 1];
   if (it0 == it1) return;  // no observed entry in this slice: keep it
-  for (int k = lane; k < WP * WP; k += 64) {
-    double s = 0.0;
-    for (int it = it0; it < it1; ++it) s += (double)partials[(int64_t)it * WP * WP + k];
-    S[k] = s;
+  {
+    // items outer, 16-byte vectors inner, two items in flight per pass
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
+    constexpr int VE = 16 / sizeof(T);
+    constexpr int NV = WP * WP / VE;  // WP is a multiple of 16
+    constexpr int PV = (NV + 63) / 64;
+    double acc[PV][VE];
+#pragma unroll
+    for (int q = 0; q < PV; ++q)
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[q][e] = 0.0;
+    auto add = [&](const V& v, int q) {
+      const T* t = (const T*)&v;
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[q][e] += (double)t[e];
+    };
+    int it = it0;
+    for (; it + 1 < it1; it += 2) {
+      const V* s0 = (const V*)(partials + (int64_t)it * WP * WP);
+      const V* s1 = s0 + NV;
+      V v0[PV], v1[PV];
+#pragma unroll
+      for (int q = 0; q < PV; ++q) {
+        const int k = lane + 64 * q;
+        if (k < NV) {
+          v0[q] = s0[k];
+          v1[q] = s1[k];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PV; ++q)
+        if (lane + 64 * q < NV) {
+          add(v0[q], q);
+          add(v1[q], q);
+        }
+    }
+    if (it < it1) {
+      const V* s0 = (const V*)(partials + (int64_t)it * WP * WP);
+#pragma unroll
+      for (int q = 0; q < PV; ++q)
+        if (lane + 64 * q < NV) add(s0[lane + 64 * q], q);
+    }
+#pragma unroll
+    for (int q = 0; q < PV; ++q) {
+      const int k = lane + 64 * q;
+      if (k < NV)
+#pragma unroll
+        for (int e = 0; e < VE; ++e) S[k * VE + e] = acc[q][e];
+    }
   }
   __syncthreads();
-  double trl = 0.0;
-  for (int k = lane; k < D; k += 64) trl += inner_K<R>(S, WP, k, k).x;
-  const double tau = wave_sum(trl) / D;
+  for (int k = lane; k < D * D; k += 64) {
+    const int i = k / D, j = k % D;
+    K[i * LD + j] = inner_K<R>(S, WP, i, j);
+  }
+  double2 h = make_double2(0.0, 0.0);
+  if (lane < D) h = inner_h<R>(S, WP, lane);
+  __syncthreads();  // S is dead from here on; M takes its place
+  const double tau = wave_sum(lane < D ? K[lane * LD + lane].x : 0.0) / D;
   const double unit = fmax(reg_floor, 0x1p-53);
   double lam = fmax(reg_rel, D * reg_floor) * tau;
   cx<T>* slice = slices + (int64_t)tile * D;
+  double2 old = make_double2(0.0, 0.0);
+  if (lane < D) old = make_double2((double)slice[lane].x, (double)slice[lane].y);
   bool ok = false;
   int attempt = 0;
   for (; attempt < 4; ++attempt) {
@@ -453,24 +503,13 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
       if (!(lam > 0.0)) break;
       lam = fmax(100.0 * lam, D * unit * tau);
     }
-    __syncthreads();
-    for (int k = lane; k < D * D; k += 64) {
-      double2 v = inner_K<R>(S, WP, k / D, k % D);
-      if (k / D == k % D) v.x += lam;
+    for (int k = lane; k < D * LD; k += 64) {
+      double2 v = K[k];
+      if (k % LD == k / LD) v.x += lam;
       M[k] = v;
     }
-    for (int k = lane; k < D; k += 64) {
-      double2 h = inner_h<R>(S, WP, k);
-      if (prox) {
-        const cx<T> old = slice[k];
-        h.x += lam * (double)old.x;
-        h.y += lam * (double)old.y;
-      }
-      rhs[k] = h;
-      sol[k] = h;
-    }
     __syncthreads();
-    ok = wave_cholesky(M, D, lane);
+    ok = lds_cholesky(M, D, LD, panel, lane);
     if (ok) break;
   }
   if (!ok) {
@@ -478,24 +517,108 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
     return;
   }
   if (attempt > 0 && lane == 0) atomicAdd(flags + 1, 1);
-  wave_chol_solve(M, sol, D, lane);
-  // one step of iterative refinement against the FP64 system rebuilt from S
-  if (lane < D) {
-    double2 res = rhs[lane];
-    for (int k = 0; k < D; ++k) {
-      double2 m = inner_K<R>(S, WP, lane, k);
-      if (k == lane) m.x += lam;
-      const double2 s = sol[k];
-      res.x -= m.x * s.x - m.y * s.y;
-      res.y -= m.x * s.y + m.y * s.x;
-    }
-    rhs[lane] = res;
+  double2 rhs = h;
+  if (prox) {
+    rhs.x += lam * old.x;
+    rhs.y += lam * old.y;
   }
+  double2 sol = rhs;
+  lds_chol_solve(M, D, LD, sol, lane);
+  // one step of iterative refinement against the assembled FP64 system
+  double2 res = rhs;
+  const double2* Krow = K + (lane < D ? lane : 0) * LD;
+  for (int j = 0; j < D; ++j) {
+    const double sx = bcast_d(sol.x, j), sy = bcast_d(sol.y, j);
+    double2 m = Krow[j];
+    if (j == lane) m.x += lam;
+    res.x -= m.x * sx - m.y * sy;
+    res.y -= m.x * sy + m.y * sx;
+  }
+  lds_chol_solve(M, D, LD, res, lane);
+  if (lane < D) slice[lane] = {T(sol.x + res.x), T(sol.y + res.y)};
+}
+
+// ---------------------------------------------------------------------------
+// environment-trie levels
+// ---------------------------------------------------------------------------
+
+// Right level p (0 <= p < L): node (u, j) = Z^(p+2)[k] * parent, where
+// k = ((ib >> p) << (p+1)) | (jb >> (L-p-1)) with ib >> p = u, and the parent
+// is node (u >> 1, j) of level p+1 (a row of Z^(L+2) when p = L-1).
+template <typename T, int R>
+__global__ __launch_bounds__(256) void env_right_level_kernel(
+    const cx<T>* cores, int64_t n, int L, int c, int p, const int32_t* node_u,
+    const int32_t* node_j, const int32_t* parent, const cx<T>* parent_vec, int count,
+    cx<T>* out) {
+  const int k = xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const uint32_t u = (uint32_t)node_u[k], j = (uint32_t)node_j[k];
+  const uint32_t key = (u << (p + 1)) | ((j / (uint32_t)c) >> (L - p - 1));
+  const cx<T>* Z = cores + inner_off(n, L, R, p + 1) + (int64_t)key * R * R;
+  cx<T> w[R];
+  load_env<T, R>(parent_vec, parent[k], w);
+  mat_vec<T, R>(Z, w);
+  cx<T>* o = out + (int64_t)k * R;
+#pragma unroll
+  for (int a = 0; a < R; ++a) o[a] = w[a];
+}
+
+// Left level p (2 <= p <= L+1): node (w, i) = parent * Z^p[k], where
+// k = ((ib >> (p-2)) << (p-1)) | (jb >> (L-p+1)) with jb >> (L-p+1) = w, and
+// the parent is node (w >> 1, i) of level p-1 (a row of Z^1 when p = 2).
+template <typename T, int R>
+__global__ __launch_bounds__(256) void env_left_level_kernel(
+    const cx<T>* cores, int64_t n, int L, int c, int p, const int32_t* node_w,
+    const int32_t* node_i, const int32_t* parent, const cx<T>* parent_vec, int count,
+    cx<T>* out) {
+  const int k = xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const uint32_t w = (uint32_t)node_w[k], i = (uint32_t)node_i[k];
+  const uint32_t key = (((i / (uint32_t)c) >> (p - 2)) << (p - 1)) | w;
+  const cx<T>* Z = cores + inner_off(n, L, R, p - 1) + (int64_t)key * R * R;
+  cx<T> v[R];
+  load_env<T, R>(parent_vec, parent[k], v);
+  vec_mat<T, R>(v, Z);
+  cx<T>* o = out + (int64_t)k * R;
+#pragma unroll
+  for (int a = 0; a < R; ++a) o[a] = v[a];
+}
+
+// Residual on the observed set from the cached left environments of the last
+// core: x = l_(L+1) . Z^(L+2)[j].  Entries in the last core's order.
+template <typename T, int R>
+__global__ __launch_bounds__(kResThreads) void residual_observed_kernel(
+    const cx<T>* lenv, const int32_t* lidx, const cx<T>* zlast, const int32_t* cols,
+    const cx<T>* vals, int64_t m, int64_t per_block, double* partial) {
+  __shared__ double s0[kResThreads], s1[kResThreads];
+  double a0 = 0.0, a1 = 0.0;
+  const int64_t beg = (int64_t)blockIdx.x * per_block;
+  const int64_t end = beg + per_block < m ? beg + per_block : m;
+  for (int64_t e = beg + threadIdx.x; e < end; e += kResThreads) {
+    cx<T> v[R], z[R];
+    load_env<T, R>(lenv, lidx[e], v);
+    load_env<T, R>(zlast, cols[e], z);
+    cx<T> x = {T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < R; ++a) cfma(x, v[a], z[a]);
+    const cx<T> t = vals[e];
+    const double dx = (double)t.x - (double)x.x, dy = (double)t.y - (double)x.y;
+    a0 += dx * dx + dy * dy;
+    a1 += (double)t.x * (double)t.x + (double)t.y * (double)t.y;
+  }
+  s0[threadIdx.x] = a0;
+  s1[threadIdx.x] = a1;
   __syncthreads();
-  wave_chol_solve(M, rhs, D, lane);
-  if (lane < D) {
-    const double2 s = sol[lane], d = rhs[lane];
-    slice[lane] = {T(s.x + d.x), T(s.y + d.y)};
+  for (int off = kResThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s0[threadIdx.x] += s0[threadIdx.x + off];
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = s0[0];
+    partial[2 * blockIdx.x + 1] = s1[0];
   }
 }
 
@@ -540,6 +663,55 @@ __global__ void random_cores_kernel(cx<T>* dst, int64_t m, uint64_t seed, double
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
+// Right level p depends on cores p+1..L+1, left level p on cores 0..p-1.
+template <typename T, int R>
+bfc_status ensure_right(Problem* P, int p, hipStream_t st) {
+  const int L = P->L;
+  if (p >= L) return BFC_OK;  // the right environment of core L is Z^(L+2) itself
+  int top = -1;
+  for (int q = L - 1; q >= p; --q)
+    if (!P->rlev[q].valid) {
+      top = q;
+      break;
+    }
+  if (top < 0) return BFC_OK;
+  cx<T>* cores = (cx<T>*)P->cores;
+  for (int q = top; q >= p; --q) {
+    EnvLevel& E = P->rlev[q];
+    const cx<T>* pv = (q == L - 1) ? cores + last_off(P->n, L, R) : (const cx<T>*)P->rlev[q + 1].vec;
+    if (E.count > 0)
+      env_right_level_kernel<T, R><<<grid_for(E.count), 256, 0, st>>>(
+          cores, P->n, L, P->c, q, E.node_a, E.node_b, E.parent, pv, E.count, (cx<T>*)E.vec);
+    BFC_HIP_TRY(hipGetLastError());
+    E.valid = true;
+  }
+  return BFC_OK;
+}
+
+template <typename T, int R>
+bfc_status ensure_left(Problem* P, int p, hipStream_t st) {
+  const int L = P->L;
+  if (p <= 1) return BFC_OK;  // the left environment of core 1 is Z^1 itself
+  int low = -1;
+  for (int q = 2; q <= p; ++q)
+    if (!P->llev[q].valid) {
+      low = q;
+      break;
+    }
+  if (low < 0) return BFC_OK;
+  cx<T>* cores = (cx<T>*)P->cores;
+  for (int q = low; q <= p; ++q) {
+    EnvLevel& E = P->llev[q];
+    const cx<T>* pv = (q == 2) ? cores : (const cx<T>*)P->llev[q - 1].vec;
+    if (E.count > 0)
+      env_left_level_kernel<T, R><<<grid_for(E.count), 256, 0, st>>>(
+          cores, P->n, L, P->c, q, E.node_a, E.node_b, E.parent, pv, E.count, (cx<T>*)E.vec);
+    BFC_HIP_TRY(hipGetLastError());
+    E.valid = true;
+  }
+  return BFC_OK;
+}
+
 template <typename T, int R>
 bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   cx<T>* cores = (cx<T>*)P->cores;
@@ -549,35 +721,75 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   const double floor_ = P->prec == BFC_C128 ? 0.0 : 0x1p-24;
   const int prox = P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0;
   const int L = P->L;
+  {
+    ProfScope ps(&P->prof, KIND_ENV, st);
+    BFC_TRY(ensure_right<T, R>(P, p, st));
+    BFC_TRY(ensure_left<T, R>(P, p, st));
+  }
+  // environment sources of core p: cached level, or a row of Z^1 / Z^(L+2)
+  const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R)
+                               : (p <= L - 1 ? (const cx<T>*)P->rlev[p].vec : nullptr);
+  const int32_t* ridx = (p == L) ? C.cols : C.rnode;
+  const cx<T>* lenv = (p == 1) ? cores : (p >= 2 ? (const cx<T>*)P->llev[p].vec : nullptr);
+  const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
   if (p == 0 || p == L + 1) {
+    cx<T>* fibers = cores + (p == 0 ? 0 : last_off(P->n, L, R));
+    const cx<T>* env = p == 0 ? renv : lenv;
+    const int32_t* idx = p == 0 ? ridx : lidx;
     {
       ProfScope ps(&P->prof, KIND_OUTER, st);
-      outer_update_kernel<T, R><<<C.nblocks, 64, 0, st>>>(
-          cores, P->n, L, P->c, p == L + 1 ? 1 : 0, C.rows, C.cols, (const cx<T>*)C.vals,
-          C.blk_off, C.nblocks, reg, floor_, prox, P->flags);
+      const unsigned grid = (unsigned)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
+      outer_update_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(
+          fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks, reg, floor_, prox,
+          P->flags);
     }
     BFC_HIP_TRY(hipGetLastError());
-    return BFC_OK;
-  }
-  if (C.nitems > 0) {
-    ProfScope ps(&P->prof, KIND_INNER_GRAM, st);
-    if (C.group_by_row)
-      inner_gram_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(cores, P->n, L, P->c, p, C.rows, C.cols,
-                                                          (const cx<T>*)C.vals, C.sub_off, C.items,
-                                                          (T*)P->partials);
-    else
-      inner_gram_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(cores, P->n, L, P->c, p, C.rows, C.cols,
-                                                          (const cx<T>*)C.vals, C.sub_off, C.items,
-                                                          (T*)P->partials);
+  } else {
+    if (C.nitems > 0) {
+      ProfScope ps(&P->prof, KIND_INNER_GRAM, st);
+      if (C.group_by_row)
+        inner_gram_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(
+            lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
+      else
+        inner_gram_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(
+            lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
+      BFC_HIP_TRY(hipGetLastError());
+    }
+    cx<T>* slices = cores + inner_off(P->n, L, R, p);
+    {
+      ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
+      inner_solve_kernel<T, R><<<C.nblocks, 64, 0, st>>>(slices, (const T*)P->partials,
+                                                         C.tile_items, reg, floor_, prox,
+                                                         P->flags);
+    }
     BFC_HIP_TRY(hipGetLastError());
   }
-  cx<T>* slices = cores + inner_off(P->n, L, R, p);
-  {
-    ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
-    inner_solve_kernel<T, R><<<C.nblocks, 64, 0, st>>>(slices, (const T*)P->partials,
-                                                       C.tile_items, reg, floor_, prox,
-                                                       P->flags);
-  }
+  // core p changed: right levels below it and left levels above it are stale
+  for (int q = 0; q < p && q < L; ++q) P->rlev[q].valid = false;
+  for (int q = p + 1; q <= L + 1; ++q)
+    if (q >= 2) P->llev[q].valid = false;
+  return BFC_OK;
+}
+
+template <typename T, int R>
+bfc_status residual_observed_t(Problem* P, double* out2, hipStream_t st) {
+  const int L = P->L;
+  BFC_TRY(ensure_left<T, R>(P, L + 1, st));
+  cx<T>* cores = (cx<T>*)P->cores;
+  const CoreLayout& C = P->lay[L + 1];
+  const cx<T>* lenv = (L + 1 == 1) ? cores : (const cx<T>*)P->llev[L + 1].vec;
+  const int32_t* lidx = (L + 1 == 1) ? C.rows : C.lnode;
+  const int64_t m = P->nnz;
+  const int64_t nblk_max = (int64_t)(P->red_len / 2);
+  int64_t per = (m + nblk_max - 1) / nblk_max;
+  per = ((per + kResThreads - 1) / kResThreads) * kResThreads;
+  if (per < kResThreads) per = kResThreads;
+  const int64_t nblk = (m + per - 1) / per;
+  ProfScope ps(&P->prof, KIND_RESIDUAL, st);
+  residual_observed_kernel<T, R><<<(unsigned)nblk, kResThreads, 0, st>>>(
+      lenv, lidx, cores + last_off(P->n, L, R), C.cols, (const cx<T>*)C.vals, m, per, P->red);
+  BFC_HIP_TRY(hipGetLastError());
+  residual_final_kernel<<<1, kResThreads, 0, st>>>(P->red, (int)nblk, out2);
   BFC_HIP_TRY(hipGetLastError());
   return BFC_OK;
 }
@@ -644,6 +856,12 @@ struct PredictF {
   }
 };
 template <typename T, int R>
+struct ResidualObservedF {
+  static bfc_status run(Problem* P, double* out2, hipStream_t st) {
+    return residual_observed_t<T, R>(P, out2, st);
+  }
+};
+template <typename T, int R>
 struct ResidualF {
   static bfc_status run(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
                         const void* vals, double* out2, hipStream_t st) {
@@ -674,10 +892,20 @@ bfc_status launch_residual(const Problem* P, int64_t m, const int32_t* rows, con
   return dispatch<ResidualF>(P->prec, P->r, P, m, rows, cols, vals, out2, st);
 }
 
+bfc_status launch_residual_observed(Problem* P, double* out2, hipStream_t st) {
+  return dispatch<ResidualObservedF>(P->prec, P->r, P, out2, st);
+}
+
+void invalidate_envs(Problem* P) {
+  for (auto& E : P->rlev) E.valid = false;
+  for (auto& E : P->llev) E.valid = false;
+}
+
 bfc_status launch_convert_cores(Problem* P, const void* src, void* dst, bool to_internal,
                                 hipStream_t st) {
   const int64_t m = P->nparams;
   if (to_internal) {
+    invalidate_envs(P);
     if (P->prec == BFC_C128)
       cores_from_c128_kernel<double><<<grid_for(m), 256, 0, st>>>((const double2*)src,
                                                                   (cx<double>*)P->cores, m);
@@ -698,6 +926,7 @@ bfc_status launch_convert_cores(Problem* P, const void* src, void* dst, bool to_
 
 bfc_status launch_random_cores(Problem* P, uint64_t seed, hipStream_t st) {
   const int64_t m = P->nparams;
+  invalidate_envs(P);
   const double sd = sqrt(0.5 / P->r);
   if (P->prec == BFC_C128)
     random_cores_kernel<double><<<grid_for(m), 256, 0, st>>>((cx<double>*)P->cores, m, seed, sd);

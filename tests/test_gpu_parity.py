@@ -148,6 +148,39 @@ def test_core_updates_c64(shape):
         cores = [z.astype(np.complex64).astype(np.complex128) for z in ref]
 
 
+def test_core_updates_any_order_c128():
+    # cached environments must follow every change of the cores, whatever the
+    # order of the updates (and across bfc_set_cores)
+    n, L, r, nnz = 128, 4, 3, 5000
+    parts, _ = _custom(n, L, r, nnz, seed=77)
+    rows, cols, vals = parts[3], parts[4], parts[5]
+    prob = _problem(parts, reg_rel=1e-8)
+    ref = parts[6]
+    order = [3, 1, 5, 0, 2, 2, 4, 0, 5, 3, 1, 4]
+    for k, p in enumerate(order):
+        if k == 6:
+            ref = [z * 1.01 for z in ref]
+            bfc.set_cores(prob, ref)
+        bfc.sweep_core(prob, p)
+        ref = oracle.update_core(ref, p, rows, cols, vals, L, reg_rel=1e-8)
+    got = _gpu_cores(prob)
+    for p in range(L + 2):
+        assert _maxrel(got[p], ref[p]) <= 1e-9, p
+    num, den = bfc.residual_observed(prob)
+    onum, oden = oracle.residual_sq(ref, rows, cols, vals, L)
+    assert num == pytest.approx(onum, rel=1e-9)
+    assert den == pytest.approx(oden, rel=1e-13)
+
+
+def test_residual_observed_matches_residual(small):
+    prob = _problem(_parts(small))
+    bfc.sweep(prob)
+    a = bfc.residual_observed(prob)
+    b = bfc.residual(prob, small.rows, small.cols, small.vals)
+    assert a[0] == pytest.approx(b[0], rel=1e-12)
+    assert a[1] == pytest.approx(b[1], rel=1e-14)
+
+
 # --------------------------------------------------------------------------
 # whole runs
 # --------------------------------------------------------------------------
