@@ -55,24 +55,35 @@ def env_flops(env_nodes, r):
     return env_nodes * 8 * r * r
 
 
-def timed_sweeps(bfc, torch, prob, data_dev, steps, warmup):
-    rows_d, cols_d, vals_d = data_dev
+KINDS = ("env", "outer", "inner_gram", "inner_solve", "residual")
+
+
+def timed_sweeps(bfc, torch, prob, steps, warmup, profile):
+    """Time `steps` iterations (sweep + train residual) on the current stream.
+
+    profile=False: sweeps replay the captured HIP graph; the region is also
+    bracketed by HIP events on the stream.  profile=True: kernels are issued
+    one by one with per-kernel HIP events (bfc_profile_*)."""
+    stream = torch.cuda.current_stream()
     for _ in range(warmup):
         bfc.sweep(prob)
         bfc.residual_observed(prob)
-    bfc.profile_enable(prob, True)
+    bfc.profile_enable(prob, profile)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     last = None
     for _ in range(steps):
         bfc.sweep(prob)
         last = bfc.residual_observed(prob)
+    ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = {k: bfc.profile_read(prob, k)
-            for k in ("env", "outer", "inner_gram", "inner_solve", "residual")}
+    kern = {k: bfc.profile_read(prob, k) for k in KINDS} if profile else None
     bfc.profile_enable(prob, False)
-    return t1 - t0, kern, last
+    return t1 - t0, ev0.elapsed_time(ev1) * 1e-3, kern, last
 
 
 def cpu_baseline(w, budget_s=25.0):
@@ -131,6 +142,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    torch.cuda.set_stream(torch.cuda.Stream(device=dev))  # default priority
     w = make_workload(args.workload)
     print(f"# workload {w.name}: n={w.n} L={w.L} r={w.r} nnz={w.nnz}", file=sys.stderr, flush=True)
     rows_d = torch.as_tensor(w.rows, dtype=torch.int32, device=dev)
@@ -140,7 +152,6 @@ def main():
     tcols_d = torch.as_tensor(w.test_cols, dtype=torch.int32, device=dev)
     tvals_d = torch.as_tensor(w.test_vals, dtype=torch.complex128, device=dev)
     cores0 = torch.as_tensor(bfc.flatten_cores(w.cores0), device=dev)
-    data = (rows_d, cols_d, vals_d)
 
     def make(prec):
         cfg = bfc.Config(n=w.n, L=w.L, r=w.r, precision=prec, reg_rel=1e-10)
@@ -152,8 +163,12 @@ def main():
 
     prob, init_s = make(args.precision)
     print(f"# init {init_s:.3f} s", file=sys.stderr, flush=True)
-    secs, kern, last = timed_sweeps(bfc, torch, prob, data, args.steps, args.warmup)
-    print(f"# timed {args.steps} steps in {secs:.4f} s", file=sys.stderr, flush=True)
+    # throughput: graph-replayed sweeps; kernel breakdown: a second timed
+    # region issuing the same kernels one by one with per-kernel HIP events
+    secs, ev_secs, _, last = timed_sweeps(bfc, torch, prob, args.steps, args.warmup, False)
+    psecs, _, kern, _ = timed_sweeps(bfc, torch, prob, args.steps, 1, True)
+    print(f"# timed {args.steps} steps in {secs:.4f} s (events {ev_secs:.4f} s; "
+          f"profiled pass {psecs:.4f} s)", file=sys.stderr, flush=True)
     value = w.nnz * args.steps / secs
     ms_per_step = 1e3 * secs / args.steps
 
@@ -164,7 +179,7 @@ def main():
         "outer": 2 * outer_flops(w.nnz, w.r),
         "env": env_flops(bfc.env_nodes(prob), w.r),
     }
-    dom = max(flops_per_sweep, key=lambda k: kern[k][0])
+    dom = max(flops_per_sweep, key=lambda k: kern[k][0])  # largest among the kernels with a flop model
     dom_ms, dom_launches = kern[dom]
     work = flops_per_sweep[dom] * args.steps
     achieved = work / (dom_ms * 1e-3) / 1e12
@@ -203,6 +218,9 @@ def main():
                    "step": "L+2 core updates + train residual"},
         "roofline": roofline,
         "kernels": kernels,
+        "timing": {"events_ms_per_step": round(1e3 * ev_secs / args.steps, 4),
+                   "profiled_ms_per_step": round(1e3 * psecs / args.steps, 4),
+                   "sweep_launch": "captured HIP graph"},
         "init_s": round(init_s, 4),
         "train_rel_err_after_timed": train_err,
     }
@@ -236,8 +254,9 @@ def main():
 
     if not args.no_fp64 and args.precision != "c128":
         p64, init64 = make("c128")
-        s64, k64, _ = timed_sweeps(bfc, torch, p64, data, max(3, args.steps // 2), 1)
         n64 = max(3, args.steps // 2)
+        s64, _, _, _ = timed_sweeps(bfc, torch, p64, n64, 1, False)
+        _, _, k64, _ = timed_sweeps(bfc, torch, p64, n64, 0, True)
         out["fp64"] = {"value": round(w.nnz * n64 / s64, 1), "unit": "entries/s",
                        "ms_per_step": round(1e3 * s64 / n64, 4), "steps": n64,
                        "kernels": {k: {"total_ms": round(v[0], 4), "launches": v[1]}

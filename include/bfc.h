@@ -135,8 +135,17 @@ bfc_status bfc_init_cores(const bfc_config* cfg, int64_t nnz,
  */
 bfc_status bfc_sweep_core(bfc_problem* p, int32_t core, void* hip_stream);
 
-/* One full ALS iteration: cores 0, 1, ..., L+1 in that order.  Asynchronous. */
+/*
+ * One full ALS iteration: cores 0, 1, ..., L+1 in that order.  Asynchronous.
+ * On a non-default stream, with graphs enabled (the default) and per-kernel
+ * profiling off, the sweep's kernels are captured once into a HIP graph and
+ * replayed on later calls; the results are the same as issuing the core
+ * updates one by one.
+ */
 bfc_status bfc_sweep(bfc_problem* p, void* hip_stream);
+
+/* Enable (default) or disable the graph replay of bfc_sweep. */
+bfc_status bfc_use_graphs(bfc_problem* p, int32_t enable);
 
 /*
  * x_ij for m listed pairs (eq. (BF_tensor_rep)), written to d_out as m

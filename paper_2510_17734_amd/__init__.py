@@ -29,4 +29,5 @@ from .api import (  # noqa: F401
     sweep_core,
     sync_status,
     unflatten_cores,
+    use_graphs,
 )

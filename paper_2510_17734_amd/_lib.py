@@ -47,6 +47,7 @@ EXPORTS = (
     "bfc_core_stats",
     "bfc_solve_counters",
     "bfc_residual_observed",
+    "bfc_use_graphs",
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
@@ -112,6 +113,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_solve_counters.restype = i32
     lib.bfc_residual_observed.argtypes = [P, ctypes.POINTER(ctypes.c_double), vp]
     lib.bfc_residual_observed.restype = i32
+    lib.bfc_use_graphs.argtypes = [P, i32]
+    lib.bfc_use_graphs.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

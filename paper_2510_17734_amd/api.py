@@ -254,3 +254,8 @@ def solve_counters(p: Problem, reset: bool = False, stream=None):
     _check(_lib.load().bfc_solve_counters(p.handle, 1 if reset else 0, out, _stream(stream)),
            "bfc_solve_counters")
     return int(out[0]), int(out[1])
+
+
+def use_graphs(p: Problem, enable: bool = True):
+    """bfc_use_graphs: replay bfc_sweep from a captured HIP graph (default on)."""
+    _check(_lib.load().bfc_use_graphs(p.handle, 1 if enable else 0), "bfc_use_graphs")

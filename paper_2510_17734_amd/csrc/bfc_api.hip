@@ -68,6 +68,8 @@ static void release_events(Profiler& pr) {
 
 static void free_problem(bfc_problem* P) {
   release_events(P->prof);
+  if (P->sweep_exec) (void)hipGraphExecDestroy(P->sweep_exec);
+  if (P->sweep_graph) (void)hipGraphDestroy(P->sweep_graph);
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
   if (P->red_host) (void)hipHostFree(P->red_host);
@@ -207,13 +209,50 @@ bfc_status bfc_sweep_core(bfc_problem* p, int32_t core, void* hip_stream) {
   return launch_sweep_core(p, core, (hipStream_t)hip_stream);
 }
 
+// The captured sweep recomputes every environment level it uses (the state
+// a sweep reaches after any previous sweep), so replaying it is equivalent to
+// issuing the L+2 core updates one by one.  After a sweep the left levels are
+// current and the right levels stale, on either path.
+static bfc_status sweep_via_graph(bfc_problem* p, hipStream_t st) {
+  if (!p->sweep_exec) {
+    invalidate_envs(p);
+    BFC_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    bfc_status s = BFC_OK;
+    for (int core = 0; core <= p->L + 1 && s == BFC_OK; ++core) s = launch_sweep_core(p, core, st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != BFC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      invalidate_envs(p);
+      return s;
+    }
+    BFC_HIP_TRY(e);
+    p->sweep_graph = g;
+    BFC_HIP_TRY(hipGraphInstantiate(&p->sweep_exec, g, nullptr, nullptr, 0));
+  }
+  BFC_HIP_TRY(hipGraphLaunch(p->sweep_exec, st));
+  for (auto& E : p->rlev) E.valid = false;
+  for (size_t q = 2; q < p->llev.size(); ++q) p->llev[q].valid = true;
+  return BFC_OK;
+}
+
 bfc_status bfc_sweep(bfc_problem* p, void* hip_stream) {
   if (!p) {
     set_error("null problem");
     return BFC_EINVAL;
   }
-  for (int core = 0; core <= p->L + 1; ++core)
-    BFC_TRY(launch_sweep_core(p, core, (hipStream_t)hip_stream));
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (p->use_graph && !p->prof.on && st != nullptr) return sweep_via_graph(p, st);
+  for (int core = 0; core <= p->L + 1; ++core) BFC_TRY(launch_sweep_core(p, core, st));
+  return BFC_OK;
+}
+
+bfc_status bfc_use_graphs(bfc_problem* p, int32_t enable) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  p->use_graph = enable != 0;
   return BFC_OK;
 }
 

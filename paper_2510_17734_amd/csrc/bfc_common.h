@@ -156,6 +156,11 @@ struct Problem {
   double* red_host = nullptr;        // pinned, 2 doubles
   std::vector<void*> allocs;         // everything hipMalloc'd
   int32_t max_items = 0;
+  // one full sweep captured as a HIP graph (launched by bfc_sweep when
+  // graphs are enabled and per-kernel profiling is off)
+  bool use_graph = true;
+  hipGraph_t sweep_graph = nullptr;
+  hipGraphExec_t sweep_exec = nullptr;
   std::vector<EnvLevel> rlev;        // index p = 0..L-1
   std::vector<EnvLevel> llev;        // index p = 2..L+1 (0, 1 unused)
   int64_t env_bytes = 0;

@@ -213,6 +213,9 @@ __device__ inline bool lds_cholesky(double2* M, int d, int ld, double2* panel, i
     const int nb = d - k0 < kNb ? d - k0 : kNb;
     double2 D[kNb][kNb];
     if (!diag_block_factor(M, ld, k0, nb, D)) return false;
+    double rinv[kNb];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) rinv[q] = 1.0 / D[q][q].x;
     double2 Li[kNb];
 #pragma unroll
     for (int q = 0; q < kNb; ++q) Li[q] = make_double2(0.0, 0.0);
@@ -227,7 +230,7 @@ __device__ inline bool lds_cholesky(double2* M, int d, int ld, double2* panel, i
           v.x -= Li[p].x * D[q][p].x + Li[p].y * D[q][p].y;
           v.y -= Li[p].y * D[q][p].x - Li[p].x * D[q][p].y;
         }
-        const double inv = 1.0 / D[q][q].x;
+        const double inv = rinv[q];
         Li[q] = make_double2(v.x * inv, v.y * inv);
         M[lane * ld + k0 + q] = Li[q];
         panel[lane * kNb + q] = Li[q];
@@ -260,11 +263,13 @@ __device__ inline bool lds_cholesky(double2* M, int d, int ld, double2* panel, i
   return true;
 }
 
-// Solve L L^H s = b with the factor of lds_cholesky.  Lane i holds b_i in a
-// register and ends with s_i; lanes >= d carry nothing of use.  Blocked by
+// Solve L L^H s = b with the factor of lds_cholesky and rdiag[k] =
+// 1 / L[k][k].  Lane i holds b_i in a register and ends with s_i; lanes >= d
+// carry nothing of use.  Blocked by
 // kNb columns; no LDS writes and no barriers: the block's running values are
 // broadcast with readlane and its triangle is read by every lane.
-__device__ inline void lds_chol_solve(const double2* M, int d, int ld, double2& b, int lane) {
+__device__ inline void lds_chol_solve(const double2* M, const double* rdiag, int d, int ld,
+                                      double2& b, int lane) {
   const int li = lane < d ? lane : 0;
   for (int k0 = 0; k0 < d; k0 += kNb) {  // L y = b
     const int nb = d - k0 < kNb ? d - k0 : kNb;
@@ -280,7 +285,7 @@ __device__ inline void lds_chol_solve(const double2* M, int d, int ld, double2& 
         v.x -= l.x * y[p].x - l.y * y[p].y;
         v.y -= l.x * y[p].y + l.y * y[p].x;
       }
-      const double inv = 1.0 / M[(k0 + q) * ld + k0 + q].x;
+      const double inv = rdiag[k0 + q];
       y[q] = make_double2(v.x * inv, v.y * inv);
       if (lane == k0 + q) b = y[q];
     }
@@ -310,7 +315,7 @@ __device__ inline void lds_chol_solve(const double2* M, int d, int ld, double2& 
         v.x -= l.x * x[p].x + l.y * x[p].y;
         v.y -= l.x * x[p].y - l.y * x[p].x;
       }
-      const double inv = 1.0 / M[(k0 + q) * ld + k0 + q].x;
+      const double inv = rdiag[k0 + q];
       x[q] = make_double2(v.x * inv, v.y * inv);
       if (lane == k0 + q) b = x[q];
     }

@@ -426,10 +426,13 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
   __shared__ double2 K[D * LD];
   __shared__ __attribute__((aligned(16))) unsigned char mbuf[G::M_BYTES];
   __shared__ double2 panel[D * kNb];
+  __shared__ double rdiag[D];
   double* S = (double*)mbuf;
   double2* M = (double2*)mbuf;
   const int lane = threadIdx.x;
-  const int tile = blockIdx.x;
+  // same XCD-contiguous mapping as the Gram items, so the slice's partial
+  // products are read from the L2 that holds them
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
   const int it0 = tile_items[tile], it1 = tile_items[tile + 1];
   if (it0 == it1) return;  // no observed entry in this slice: keep it
   {
@@ -522,8 +525,10 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
     rhs.x += lam * old.x;
     rhs.y += lam * old.y;
   }
+  if (lane < D) rdiag[lane] = 1.0 / M[lane * LD + lane].x;
+  __syncthreads();
   double2 sol = rhs;
-  lds_chol_solve(M, D, LD, sol, lane);
+  lds_chol_solve(M, rdiag, D, LD, sol, lane);
   // one step of iterative refinement against the assembled FP64 system
   double2 res = rhs;
   const double2* Krow = K + (lane < D ? lane : 0) * LD;
@@ -534,7 +539,7 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
     res.x -= m.x * sx - m.y * sy;
     res.y -= m.x * sy + m.y * sx;
   }
-  lds_chol_solve(M, D, LD, res, lane);
+  lds_chol_solve(M, rdiag, D, LD, res, lane);
   if (lane < D) slice[lane] = {T(sol.x + res.x), T(sol.y + res.y)};
 }
 

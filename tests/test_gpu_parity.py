@@ -172,6 +172,29 @@ def test_core_updates_any_order_c128():
     assert den == pytest.approx(oden, rel=1e-13)
 
 
+def test_graph_sweeps_match_stream_sweeps(small):
+    # the captured-graph sweep replays exactly the kernels of the one-by-one
+    # path, also when single core updates are interleaved with it
+    st = torch.cuda.Stream()
+    outs = []
+    for graphs in (True, False):
+        with torch.cuda.stream(st):
+            prob = _problem(_parts(small), precision="c64")
+            bfc.use_graphs(prob, graphs)
+            bfc.sweep(prob)
+            bfc.sweep(prob)
+            bfc.sweep_core(prob, 2)
+            bfc.sweep_core(prob, 0)
+            bfc.sweep(prob)
+            bfc.set_cores(prob, bfc.get_cores(prob))
+            bfc.sweep(prob)
+            outs.append(bfc.get_cores(prob).cpu().numpy())
+            outs.append(bfc.residual_observed(prob))
+            prob.close()
+    assert np.array_equal(outs[0], outs[2])
+    assert outs[1] == outs[3]
+
+
 def test_residual_observed_matches_residual(small):
     prob = _problem(_parts(small))
     bfc.sweep(prob)
