@@ -73,8 +73,7 @@ typedef int32_t bfc_status;
 
 /* arithmetic modes */
 #define BFC_C128 0        /* complex128 cores and contractions, FP64 Gram, FP64 solves        */
-#define BFC_C64 1         /* complex64 cores and contractions, FP32 Gram, FP64 solves + one
-                             step of iterative refinement                                      */
+#define BFC_C64 1         /* complex64 cores and contractions, FP32 Gram, FP64 solves          */
 #define BFC_C64_BF16GRAM 2 /* as BFC_C64 but the Gram/right-hand-side products take bf16
                              inputs (FP32 accumulation); the FP64 solve is followed by one
                              refinement step against the FP32 normal-equation residual

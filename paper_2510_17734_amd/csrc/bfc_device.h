@@ -154,11 +154,17 @@ struct Mfma<double> {
 };
 
 // ---------------------------------------------------------------------------
-// Hermitian positive definite solve by one wavefront (a workgroup of exactly
-// 64 threads, so __syncthreads is a wavefront barrier), d <= 64 unknowns.
+// Hermitian positive definite solve by one workgroup, d <= 64 unknowns.
 // M is row-major with an odd leading dimension ld (element (i, j) at
-// i*ld + j): a row walk across lanes (stride ld) and a column walk
-// (consecutive j) both touch distinct LDS banks.  Lane i owns row i.
+// i*ld + j), so a row walk across lanes (stride ld) and a column walk
+// (consecutive j) both touch distinct LDS banks.
+//
+// Right-looking blocked Cholesky, panel width kNb.  Per panel every thread
+// factors the kNb x kNb diagonal block in registers and inverts the factor
+// (Di = L_BB^-1); the rows below then need no substitution chain
+// (L_i = a_i Di^H), and the trailing lower triangle is split evenly over the
+// workgroup's threads.  The triangular solves reuse the Di blocks, so a panel
+// of a solve is one broadcast and two short matrix-vector products.
 // ---------------------------------------------------------------------------
 
 // Uniform-lane broadcast of a double (lane index in a scalar register).
@@ -168,167 +174,206 @@ __device__ inline double bcast_d(double x, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// Blocked factorization, panel width kNb: per panel the kNb x kNb diagonal
-// block is factored redundantly in every lane's registers, the rows below
-// solve for their panel entries, and the trailing update subtracts a rank-kNb
-// product.  panel (d x kNb values of LDS) holds the panel for the trailing
-// reads, an array the row updates never write.
 constexpr int kNb = 4;
+constexpr int kPanelLd = kNb + 1;  // odd count of 16-byte values per panel row
 
-// Factor the nb x nb lower block at (k0, k0) of M into D (registers).
-__device__ __attribute__((always_inline)) inline bool diag_block_factor(const double2* M, int ld,
-                                                                         int k0, int nb,
-                                                                         double2 (&D)[kNb][kNb]) {
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cmul_conj(double2 a, double2 b) {  // a * conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate and two Newton steps
+// y <- y (3 - x y^2) / 2, each of which doubles the correct bits.
+__device__ __attribute__((always_inline)) inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// Factor the nb x nb lower diagonal block at (k0, k0) of M and return the
+// inverse of its factor in Di (lower triangular; rows and columns >= nb are
+// the identity).  False if a pivot is not positive; every thread reads the
+// same values and reaches the same answer.
+__device__ __attribute__((always_inline)) inline bool diag_block_inverse(
+    const double2* M, int ld, int k0, int nb, double2 (&Di)[kNb][kNb]) {
+  double2 D[kNb][kNb];
 #pragma unroll
   for (int a = 0; a < kNb; ++a)
 #pragma unroll
     for (int b = 0; b <= a; ++b)
       D[a][b] = (a < nb) ? M[(k0 + a) * ld + k0 + b] : make_double2(a == b ? 1.0 : 0.0, 0.0);
+  double inv[kNb];
 #pragma unroll
   for (int k = 0; k < kNb; ++k) {
     const double piv = D[k][k].x;
     if (!(piv > 0.0)) return false;
-    const double lkk = sqrt(piv), inv = 1.0 / lkk;
-    D[k][k] = make_double2(lkk, 0.0);
+    inv[k] = rsqrt_nr(piv);  // 1 / L[k][k]
 #pragma unroll
     for (int i = k + 1; i < kNb; ++i) {
-      D[i][k].x *= inv;
-      D[i][k].y *= inv;
+      D[i][k].x *= inv[k];
+      D[i][k].y *= inv[k];
     }
 #pragma unroll
     for (int j = k + 1; j < kNb; ++j)
 #pragma unroll
       for (int i = j; i < kNb; ++i) {
-        D[i][j].x -= D[i][k].x * D[j][k].x + D[i][k].y * D[j][k].y;
-        D[i][j].y -= D[i][k].y * D[j][k].x - D[i][k].x * D[j][k].y;
+        const double2 t = cmul_conj(D[i][k], D[j][k]);
+        D[i][j].x -= t.x;
+        D[i][j].y -= t.y;
       }
+  }
+  // Di[i][j] = -inv[i] * sum_{k=j}^{i-1} D[i][k] Di[k][j]
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+#pragma unroll
+    for (int i = 0; i < j; ++i) Di[i][j] = make_double2(0.0, 0.0);
+    Di[j][j] = make_double2(inv[j], 0.0);
+#pragma unroll
+    for (int i = j + 1; i < kNb; ++i) {
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = j; k < i; ++k) {
+        const double2 t = cmul(D[i][k], Di[k][j]);
+        s.x += t.x;
+        s.y += t.y;
+      }
+      Di[i][j] = make_double2(-inv[i] * s.x, -inv[i] * s.y);
+    }
   }
   return true;
 }
 
-// In-place lower Cholesky factor of the d x d matrix M.  Returns false if a
-// pivot is not positive (the result is the same in every lane).
-__device__ inline bool lds_cholesky(double2* M, int d, int ld, double2* panel, int lane) {
+// Row a and column b (b <= a) of entry e of a packed lower triangle.
+__device__ __attribute__((always_inline)) inline void tri_coords(int e, int& a, int& b) {
+  int t = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  if ((t + 1) * (t + 2) / 2 <= e) ++t;
+  if (t * (t + 1) / 2 > e) --t;
+  a = t;
+  b = e - t * (t + 1) / 2;
+}
+
+// In-place blocked lower Cholesky factor of the d x d matrix M by NT threads
+// (the whole workgroup; tid = threadIdx.x), with row d of M bordering it:
+// the factor of [[K, b], [b^H, *]] has y^H = (L^-1 b)^H in its last row, so
+// holding conj(b) in row d on entry gives conj(L^-1 b) there on exit (the
+// forward substitution rides along with the factorization).  Below the
+// diagonal blocks M receives L; the diagonal blocks of M are left as partial
+// updates, and dinv[(k0 / kNb) * kNb * kNb + a * kNb + b] receives
+// L_BB^-1[a][b] instead.  panel is (d + 1) * kPanelLd values of scratch.
+// Returns false (in every thread) if a pivot is not positive.
+template <int NT>
+__device__ __attribute__((always_inline)) inline bool wg_cholesky(double2* M, int d, int ld,
+                                                                  double2* panel, double2* dinv,
+                                                                  int tid) {
+#pragma unroll 1
   for (int k0 = 0; k0 < d; k0 += kNb) {
     const int nb = d - k0 < kNb ? d - k0 : kNb;
-    double2 D[kNb][kNb];
-    if (!diag_block_factor(M, ld, k0, nb, D)) return false;
-    double rinv[kNb];
+    double2 Di[kNb][kNb];
+    if (!diag_block_inverse(M, ld, k0, nb, Di)) return false;
+    const int r0 = k0 + nb, m = d + 1 - r0;  // rows below the block, border included
+    for (int t = tid; t < m; t += NT) {
+      double2* row = M + (r0 + t) * ld + k0;
+      double2 a[kNb];
 #pragma unroll
-    for (int q = 0; q < kNb; ++q) rinv[q] = 1.0 / D[q][q].x;
-    double2 Li[kNb];
+      for (int q = 0; q < kNb; ++q) a[q] = q < nb ? row[q] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int q = 0; q < kNb; ++q) Li[q] = make_double2(0.0, 0.0);
-    if (lane >= k0 + nb && lane < d) {
-      // L_i L_D^H = a_i, solved by forward substitution over the panel
+      for (int q = 0; q < kNb; ++q) {  // L_i[q] = sum_{p<=q} a[p] conj(Di[q][p])
+        double2 l = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < kNb; ++q) {
-        if (q >= nb) break;
-        double2 v = M[lane * ld + k0 + q];
-#pragma unroll
-        for (int p = 0; p < q; ++p) {  // v -= L_i[p] conj(L_D[q][p])
-          v.x -= Li[p].x * D[q][p].x + Li[p].y * D[q][p].y;
-          v.y -= Li[p].y * D[q][p].x - Li[p].x * D[q][p].y;
+        for (int p = 0; p <= q; ++p) {
+          const double2 s = cmul_conj(a[p], Di[q][p]);
+          l.x += s.x;
+          l.y += s.y;
         }
-        const double inv = rinv[q];
-        Li[q] = make_double2(v.x * inv, v.y * inv);
-        M[lane * ld + k0 + q] = Li[q];
-        panel[lane * kNb + q] = Li[q];
+        if (q < nb) row[q] = l;
+        panel[(r0 + t) * kPanelLd + q] = l;
       }
-    } else if (lane >= k0 && lane < k0 + nb) {
-      const int a = lane - k0;
+    }
+    if (tid < kNb * kNb) {
 #pragma unroll
-      for (int q = 0; q < kNb; ++q)
+      for (int a = 0; a < kNb; ++a)
 #pragma unroll
-        for (int r = 0; r < kNb; ++r)
-          if (r == a && q <= r) M[lane * ld + k0 + q] = D[r][q];
+        for (int b = 0; b < kNb; ++b)
+          if (tid == a * kNb + b) dinv[k0 * kNb + tid] = Di[a][b];
     }
     __syncthreads();
-    if (lane >= k0 + nb && lane < d) {
-      double2* row = M + lane * ld;
-      for (int j = k0 + nb; j <= lane; ++j) {
-        const double2* pj = panel + j * kNb;  // same address in every lane
-        double2 m = row[j];
+    // lower triangle of the trailing rows; the border's own diagonal entry
+    // (the last one) is never used and is skipped
+    const int ne = m * (m + 1) / 2 - 1;
+    for (int e = tid; e < ne; e += NT) {
+      int a, b;
+      tri_coords(e, a, b);
+      const double2* pi = panel + (r0 + a) * kPanelLd;
+      const double2* pj = panel + (r0 + b) * kPanelLd;
+      double2* mij = M + (r0 + a) * ld + r0 + b;
+      double2 v = *mij;
 #pragma unroll
-        for (int q = 0; q < kNb; ++q) {
-          const double2 c = pj[q];
-          m.x -= Li[q].x * c.x + Li[q].y * c.y;  // m -= L_i[q] conj(L_j[q])
-          m.y -= Li[q].y * c.x - Li[q].x * c.y;
-        }
-        row[j] = m;
+      for (int q = 0; q < kNb; ++q) {
+        const double2 s = cmul_conj(pi[q], pj[q]);
+        v.x -= s.x;
+        v.y -= s.y;
       }
+      *mij = v;
     }
     __syncthreads();
   }
   return true;
 }
 
-// Solve L L^H s = b with the factor of lds_cholesky and rdiag[k] =
-// 1 / L[k][k].  Lane i holds b_i in a register and ends with s_i; lanes >= d
-// carry nothing of use.  Blocked by
-// kNb columns; no LDS writes and no barriers: the block's running values are
-// broadcast with readlane and its triangle is read by every lane.
-__device__ inline void lds_chol_solve(const double2* M, const double* rdiag, int d, int ld,
-                                      double2& b, int lane) {
+// Solve L^H s = y with the factor of wg_cholesky, by one wavefront: lane i
+// holds y_i in a register and ends with s_i (lanes >= d carry nothing of
+// use).  Per diagonal block: broadcast the block's running values, multiply
+// by L_BB^-H, and subtract the block's contribution from the rows above.
+// Reads only LDS (no writes, no barriers).
+__device__ __attribute__((always_inline)) inline void wave_back_solve(const double2* M,
+                                                                      const double2* dinv, int d,
+                                                                      int ld, double2& b,
+                                                                      int lane) {
   const int li = lane < d ? lane : 0;
-  for (int k0 = 0; k0 < d; k0 += kNb) {  // L y = b
-    const int nb = d - k0 < kNb ? d - k0 : kNb;
-    double2 y[kNb];
-#pragma unroll
-    for (int q = 0; q < kNb; ++q) {
-      y[q] = make_double2(0.0, 0.0);
-      if (q >= nb) continue;
-      double2 v = make_double2(bcast_d(b.x, k0 + q), bcast_d(b.y, k0 + q));
-#pragma unroll
-      for (int p = 0; p < q; ++p) {
-        const double2 l = M[(k0 + q) * ld + k0 + p];
-        v.x -= l.x * y[p].x - l.y * y[p].y;
-        v.y -= l.x * y[p].y + l.y * y[p].x;
-      }
-      const double inv = rdiag[k0 + q];
-      y[q] = make_double2(v.x * inv, v.y * inv);
-      if (lane == k0 + q) b = y[q];
-    }
-    if (lane >= k0 + nb && lane < d) {
-#pragma unroll
-      for (int q = 0; q < kNb; ++q) {
-        if (q >= nb) break;
-        const double2 l = M[li * ld + k0 + q];
-        b.x -= l.x * y[q].x - l.y * y[q].y;
-        b.y -= l.x * y[q].y + l.y * y[q].x;
-      }
-    }
-  }
   const int last = ((d - 1) / kNb) * kNb;
-  for (int k0 = last; k0 >= 0; k0 -= kNb) {  // L^H s = y
+  for (int k0 = last; k0 >= 0; k0 -= kNb) {
     const int nb = d - k0 < kNb ? d - k0 : kNb;
-    double2 x[kNb];
+    const double2* Di = dinv + k0 * kNb;
+    double2 l[kNb];
 #pragma unroll
-    for (int q = kNb - 1; q >= 0; --q) {
-      x[q] = make_double2(0.0, 0.0);
-      if (q >= nb) continue;
-      double2 v = make_double2(bcast_d(b.x, k0 + q), bcast_d(b.y, k0 + q));
+    for (int q = 0; q < kNb; ++q) l[q] = q < nb ? M[(k0 + q) * ld + li] : make_double2(0.0, 0.0);
+    double2 bb[kNb], s[kNb];
 #pragma unroll
-      for (int p = q + 1; p < kNb; ++p) {  // v -= conj(L[k0+p][k0+q]) s_p
-        if (p >= nb) break;
-        const double2 l = M[(k0 + p) * ld + k0 + q];
-        v.x -= l.x * x[p].x + l.y * x[p].y;
-        v.y -= l.x * x[p].y - l.y * x[p].x;
+    for (int q = 0; q < kNb; ++q)
+      bb[q] = q < nb ? make_double2(bcast_d(b.x, k0 + q), bcast_d(b.y, k0 + q))
+                     : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) {  // s[q] = sum_{p>=q} conj(Di[p][q]) bb[p]
+      s[q] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int p = q; p < kNb; ++p) {
+        const double2 t = cmul_conj(bb[p], Di[p * kNb + q]);
+        s[q].x += t.x;
+        s[q].y += t.y;
       }
-      const double inv = rdiag[k0 + q];
-      x[q] = make_double2(v.x * inv, v.y * inv);
-      if (lane == k0 + q) b = x[q];
+      if (lane == k0 + q) b = s[q];
     }
-    if (lane < k0) {
+    if (lane < k0) {  // b_i -= conj(L[k0+q][i]) s_q
 #pragma unroll
       for (int q = 0; q < kNb; ++q) {
-        if (q >= nb) break;
-        const double2 l = M[(k0 + q) * ld + li];  // conj(L[k0+q][lane]) s_q
-        b.x -= l.x * x[q].x + l.y * x[q].y;
-        b.y -= l.x * x[q].y - l.y * x[q].x;
+        const double2 t = cmul_conj(s[q], l[q]);
+        b.x -= t.x;
+        b.y -= t.y;
       }
     }
   }
+}
+
+// Orders LDS writes of one wavefront before its later LDS reads by other
+// lanes of the same wavefront.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------------------

@@ -229,33 +229,18 @@ __global__ __launch_bounds__(kOuterThreads) void outer_update_kernel(
     return;
   }
   if (attempt > 0) atomicAdd(flags + 1, 1);
-  double2 rhs[R], sol[R];
+  double2 sol[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    rhs[k] = make_double2((double)hx[k], (double)hy[k]);
+    sol[k] = make_double2((double)hx[k], (double)hy[k]);
     if (prox) {
-      rhs[k].x += lam * (double)fiber[k].x;
-      rhs[k].y += lam * (double)fiber[k].y;
+      sol[k].x += lam * (double)fiber[k].x;
+      sol[k].y += lam * (double)fiber[k].y;
     }
-    sol[k] = rhs[k];
   }
   serial_chol_solve<R>(M, sol);
-  // one refinement step against the assembled FP64 system
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      int re, im, sg;
-      herm_coord(i, j, R, re, im, sg);
-      double mx = (double)acc[re], my = im >= 0 ? sg * (double)acc[im] : 0.0;
-      if (i == j) mx += lam;
-      rhs[i].x -= mx * sol[j].x - my * sol[j].y;
-      rhs[i].y -= mx * sol[j].y + my * sol[j].x;
-    }
-  }
-  serial_chol_solve<R>(M, rhs);
-#pragma unroll
-  for (int k = 0; k < R; ++k) fiber[k] = {T(sol[k].x + rhs[k].x), T(sol[k].y + rhs[k].y)};
+  for (int k = 0; k < R; ++k) fiber[k] = {T(sol[k].x), T(sol[k].y)};
 }
 
 // ---------------------------------------------------------------------------
@@ -399,13 +384,12 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// inner cores: per-slice sum of partials, FP64 Hermitian solve (one wavefront)
+// inner cores: per-slice sum of partials, FP64 Hermitian solve (one workgroup)
 // ---------------------------------------------------------------------------
-// One wavefront per slice: sum the work items' partial products in a fixed
-// order, assemble the Hermitian FP64 system (odd leading
-// dimension, row-major) and solve it with the regularization ladder and one refinement
-// step.  LDS: the real partial sum S is only needed to assemble K and h, so
-// the factor M reuses its space.
+// The work items' partial products are summed in a fixed order, so results do
+// not depend on scheduling.  K and the factor are row-major with an odd
+// leading dimension.  LDS: the real partial sum S is only needed to assemble
+// K and h, so the factor M reuses its space.
 template <int R>
 struct SolveGeom {
   static constexpr int D = R * R;
@@ -413,23 +397,28 @@ struct SolveGeom {
   static constexpr int LD = (D % 2) ? D : D + 1;
   static constexpr int K_BYTES = D * LD * 16;
   static constexpr int S_BYTES = WP * WP * 8;
-  static constexpr int M_BYTES = (K_BYTES > S_BYTES ? K_BYTES : S_BYTES);
+  static constexpr int F_BYTES = (D + 1) * LD * 16;  // factor and its border row
+  static constexpr int M_BYTES = (F_BYTES > S_BYTES ? F_BYTES : S_BYTES);
+  static constexpr int NP = (D + kNb - 1) / kNb;  // diagonal blocks
 };
+constexpr int kSolveThreads = 256;
 
+// One workgroup per slice: sum the slice's partial products (S), assemble the
+// Hermitian system (K, h), factor K + lam I bordered by the right-hand side
+// h + lam s_old (regularization ladder), back-substitute, write the slice.
 template <typename T, int R>
-__global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T* partials,
-                                                         const int32_t* tile_items,
-                                                         double reg_rel, double reg_floor,
-                                                         int prox, int32_t* flags) {
+__global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2))) void inner_solve_kernel(
+    cx<T>* slices, const T* partials, const int32_t* tile_items, double reg_rel,
+    double reg_floor, int prox, int32_t* flags) {
   typedef SolveGeom<R> G;
-  constexpr int D = G::D, WP = G::WP, LD = G::LD;
+  constexpr int D = G::D, WP = G::WP, LD = G::LD, NT = kSolveThreads;
   __shared__ double2 K[D * LD];
   __shared__ __attribute__((aligned(16))) unsigned char mbuf[G::M_BYTES];
-  __shared__ double2 panel[D * kNb];
-  __shared__ double rdiag[D];
+  __shared__ double2 panel[(D + 1) * kPanelLd];
+  __shared__ double2 dinv[G::NP * kNb * kNb];
   double* S = (double*)mbuf;
   double2* M = (double2*)mbuf;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   // same XCD-contiguous mapping as the Gram items, so the slice's partial
   // products are read from the L2 that holds them
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -440,7 +429,7 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
     constexpr int VE = 16 / sizeof(T);
     constexpr int NV = WP * WP / VE;  // WP is a multiple of 16
-    constexpr int PV = (NV + 63) / 64;
+    constexpr int PV = (NV + NT - 1) / NT;
     double acc[PV][VE];
 #pragma unroll
     for (int q = 0; q < PV; ++q)
@@ -458,7 +447,7 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
       V v0[PV], v1[PV];
 #pragma unroll
       for (int q = 0; q < PV; ++q) {
-        const int k = lane + 64 * q;
+        const int k = tid + NT * q;
         if (k < NV) {
           v0[q] = s0[k];
           v1[q] = s1[k];
@@ -466,7 +455,7 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
       }
 #pragma unroll
       for (int q = 0; q < PV; ++q)
-        if (lane + 64 * q < NV) {
+        if (tid + NT * q < NV) {
           add(v0[q], q);
           add(v1[q], q);
         }
@@ -475,30 +464,32 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
       const V* s0 = (const V*)(partials + (int64_t)it * WP * WP);
 #pragma unroll
       for (int q = 0; q < PV; ++q)
-        if (lane + 64 * q < NV) add(s0[lane + 64 * q], q);
+        if (tid + NT * q < NV) add(s0[tid + NT * q], q);
     }
 #pragma unroll
     for (int q = 0; q < PV; ++q) {
-      const int k = lane + 64 * q;
+      const int k = tid + NT * q;
       if (k < NV)
 #pragma unroll
         for (int e = 0; e < VE; ++e) S[k * VE + e] = acc[q][e];
     }
   }
   __syncthreads();
-  for (int k = lane; k < D * D; k += 64) {
+  for (int k = tid; k < D * D; k += NT) {
     const int i = k / D, j = k % D;
     K[i * LD + j] = inner_K<R>(S, WP, i, j);
   }
   double2 h = make_double2(0.0, 0.0);
-  if (lane < D) h = inner_h<R>(S, WP, lane);
+  if (tid < D) h = inner_h<R>(S, WP, tid);
   __syncthreads();  // S is dead from here on; M takes its place
-  const double tau = wave_sum(lane < D ? K[lane * LD + lane].x : 0.0) / D;
+  double tr = 0.0;
+  for (int i = 0; i < D; ++i) tr += K[i * LD + i].x;  // same order in every thread
+  const double tau = tr / D;
   const double unit = fmax(reg_floor, 0x1p-53);
   double lam = fmax(reg_rel, D * reg_floor) * tau;
   cx<T>* slice = slices + (int64_t)tile * D;
   double2 old = make_double2(0.0, 0.0);
-  if (lane < D) old = make_double2((double)slice[lane].x, (double)slice[lane].y);
+  if (prox && tid < D) old = make_double2((double)slice[tid].x, (double)slice[tid].y);
   bool ok = false;
   int attempt = 0;
   for (; attempt < 4; ++attempt) {
@@ -506,41 +497,30 @@ __global__ __launch_bounds__(64) void inner_solve_kernel(cx<T>* slices, const T*
       if (!(lam > 0.0)) break;
       lam = fmax(100.0 * lam, D * unit * tau);
     }
-    for (int k = lane; k < D * LD; k += 64) {
+    for (int k = tid; k < D * LD; k += NT) {
       double2 v = K[k];
       if (k % LD == k / LD) v.x += lam;
       M[k] = v;
     }
+    if (tid < D)  // border row: conj(h + lam old)
+      M[D * LD + tid] = make_double2(h.x + lam * old.x, -(h.y + lam * old.y));
     __syncthreads();
-    ok = lds_cholesky(M, D, LD, panel, lane);
+    ok = wg_cholesky<NT>(M, D, LD, panel, dinv, tid);
     if (ok) break;
   }
   if (!ok) {
-    if (lane == 0) atomicAdd(flags, 1);
+    if (tid == 0) atomicAdd(flags, 1);
     return;
   }
-  if (attempt > 0 && lane == 0) atomicAdd(flags + 1, 1);
-  double2 rhs = h;
-  if (prox) {
-    rhs.x += lam * old.x;
-    rhs.y += lam * old.y;
+  if (attempt > 0 && tid == 0) atomicAdd(flags + 1, 1);
+  if (tid >= 64) return;  // one wavefront solves; no barriers below
+  double2 y = make_double2(0.0, 0.0);
+  if (lane < D) {
+    const double2 t = M[D * LD + lane];
+    y = make_double2(t.x, -t.y);
   }
-  if (lane < D) rdiag[lane] = 1.0 / M[lane * LD + lane].x;
-  __syncthreads();
-  double2 sol = rhs;
-  lds_chol_solve(M, rdiag, D, LD, sol, lane);
-  // one step of iterative refinement against the assembled FP64 system
-  double2 res = rhs;
-  const double2* Krow = K + (lane < D ? lane : 0) * LD;
-  for (int j = 0; j < D; ++j) {
-    const double sx = bcast_d(sol.x, j), sy = bcast_d(sol.y, j);
-    double2 m = Krow[j];
-    if (j == lane) m.x += lam;
-    res.x -= m.x * sx - m.y * sy;
-    res.y -= m.x * sy + m.y * sx;
-  }
-  lds_chol_solve(M, rdiag, D, LD, res, lane);
-  if (lane < D) slice[lane] = {T(sol.x + res.x), T(sol.y + res.y)};
+  wave_back_solve(M, dinv, D, LD, y, lane);
+  if (lane < D) slice[lane] = {T(y.x), T(y.y)};
 }
 
 // ---------------------------------------------------------------------------
@@ -763,7 +743,7 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
     cx<T>* slices = cores + inner_off(P->n, L, R, p);
     {
       ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
-      inner_solve_kernel<T, R><<<C.nblocks, 64, 0, st>>>(slices, (const T*)P->partials,
+      inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(slices, (const T*)P->partials,
                                                          C.tile_items, reg, floor_, prox,
                                                          P->flags);
     }
