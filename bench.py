@@ -55,6 +55,84 @@ def env_flops(env_nodes, r):
     return env_nodes * 8 * r * r
 
 
+def kernel_models(stats, w, cbytes, env_total):
+    """Algorithmic HBM bytes and flops of one sweep, per kernel kind.
+
+    Bytes count every array a kernel must touch once: per observed entry its
+    value and indices; every environment vector (r complex values) and every
+    core row it reads; the partial products it writes or reads; nothing for
+    re-reads that a cache could serve.  cbytes is the size of one complex
+    value (8 for complex64, 16 for complex128)."""
+    r, n, L, nnz = w.r, w.n, w.L, w.nnz
+    d = r * r
+    wp = (d + 2 * r + 15) // 16 * 16
+    real = cbytes // 2
+    vec = r * cbytes
+    m = {}
+    gb = gf = sb = sf = 0
+    for p in range(1, L + 1):
+        st = stats[p]
+        lnodes = st["left_env_nodes"] or n   # rows of Z^1 when p = 1
+        rnodes = st["right_env_nodes"] or n  # rows of Z^(L+2) when p = L
+        gb += nnz * (cbytes + 8) + (lnodes + rnodes) * vec + st["subgroups"] * 4 \
+            + st["items"] * wp * wp * real
+        gf += inner_gram_flops(st, nnz, r)
+        sb += st["items"] * wp * wp * real + 2 * st["blocks"] * d * cbytes
+        sf += st["blocks"] * (4 * d ** 3 // 3 + 8 * d * d)  # Cholesky + one triangular solve
+    m["inner_gram"] = (gb, gf)
+    m["inner_solve"] = (sb, sf)
+    ob = of = 0
+    for p in (0, L + 1):
+        st = stats[p]
+        nodes = st["right_env_nodes"] + st["left_env_nodes"]
+        ob += nnz * (cbytes + 4) + nodes * vec + 2 * n * r * cbytes + (st["blocks"] + 1) * 4
+        of += outer_flops(nnz, r)
+    m["outer"] = (ob, of)
+    # a node writes its vector and reads its parent's, its two ids and its
+    # parent index (the core slices it multiplies are a few MB, cache-resident)
+    m["env"] = (env_total * (2 * vec + 12), env_flops(env_total, r))
+    m["residual"] = (nnz * (8 + cbytes) + stats[L + 1]["left_env_nodes"] * vec + n * vec,
+                     nnz * 8 * r)
+    return m
+
+
+def source_digest():
+    """SHA-256 over the HIP sources: a stored counter reading belongs to the
+    kernels built from exactly these files."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_17734_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload, or None when there is none or the sources have changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    digest, table = None, {}
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("source_sha256:"):
+                digest = ln.split(":", 1)[1].strip()
+            cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+            if len(cells) >= 6 and cells[0].startswith("`") and cells[0] != "`kernel`":
+                try:
+                    table[cells[0].strip("`")] = float(cells[5])
+                except ValueError:
+                    pass
+    if digest != source_digest():
+        return None
+    return table.get(kernel)
+
+
 KINDS = ("env", "outer", "inner_gram", "inner_solve", "residual")
 
 
@@ -117,6 +195,127 @@ def cpu_baseline(w, budget_s=25.0):
     }
 
 
+KIND_PATTERNS = (("inner_gram", "inner_gram_kernel"), ("inner_solve", "inner_solve_kernel"),
+                 ("outer", "outer_update_kernel"), ("env", "_level_kernel"),
+                 ("residual", "residual_observed_kernel"))
+
+
+def kernel_kind(name):
+    for kind, pat in KIND_PATTERNS:
+        if pat in name:
+            return kind
+    return None
+
+
+def find_file(root, suffix):
+    for dirpath, _, files in os.walk(root):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(dirpath, f)
+    raise FileNotFoundError(f"no *{suffix} under {root}")
+
+
+def pmc_summary(fetch_dir, write_dir, copy_mib, bench_json, out, command):
+    """Per-kernel HBM traffic from two rocprofv3 counter runs (FETCH_SIZE and
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+    for the calibration copy of copy_mib MiB (the largest copyBuffer
+    dispatch), written as a markdown summary that bench.py reads back."""
+    import csv
+
+    per = {}
+    copies = {}
+    for counter, root in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        with open(find_file(root, "counter_collection.csv")) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                name, val = row["Kernel_Name"], float(row["Counter_Value"])
+                if "copyBuffer" in name:
+                    copies[counter] = max(copies.get(counter, 0.0), val)
+                kind = kernel_kind(name)
+                if kind:
+                    per.setdefault((kind, counter), []).append(val)
+    expect = copy_mib * 1024.0
+    scale = {c: expect / copies[c] for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    alg = {}
+    if bench_json:
+        with open(bench_json) as fh:
+            for ln in fh:
+                if ln.startswith("{"):
+                    rec = json.loads(ln)
+                    alg = rec.get("algorithmic_bytes_per_launch", {})
+    lines = [f"# HBM traffic per kernel launch: {rec['config']['workload']}, "
+             f"{rec['config']['precision']}" if alg else "# HBM traffic per kernel launch", "",
+             "Two `rocprofv3 --pmc` runs of the same bench command (one counter each),",
+             f"with a {copy_mib} MiB device-to-device copy as calibration:", "", "```"]
+    lines += command
+    lines += ["```", "",
+              f"calibration: copy of {copy_mib} MiB read FETCH_SIZE {copies['FETCH_SIZE']:.1f} KiB "
+              f"and WRITE_SIZE {copies['WRITE_SIZE']:.1f} KiB (expected {expect:.1f} each); "
+              f"scale FETCH x{scale['FETCH_SIZE']:.4f}, WRITE x{scale['WRITE_SIZE']:.4f}", "",
+              f"source_sha256: {source_digest()}", "",
+              "| kernel | dispatches | FETCH KiB/dispatch | WRITE KiB/dispatch | "
+              "scaled MB/launch | HBM bytes per launch | algorithmic bytes per launch | ratio |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for kind, _ in KIND_PATTERNS:
+        f = per.get((kind, "FETCH_SIZE"))
+        wv = per.get((kind, "WRITE_SIZE"))
+        if not f or not wv:
+            continue
+        fk, wk = sum(f) / len(f), sum(wv) / len(wv)
+        hbm = (fk * scale["FETCH_SIZE"] + wk * scale["WRITE_SIZE"]) * 1024.0
+        a_b = alg.get(kind)
+        ratio = f"{hbm / a_b:.3f}" if a_b else "-"
+        lines.append(f"| `{kind}` | {len(f)} | {fk:.1f} | {wk:.1f} | {hbm / 1e6:.2f} | {hbm:.0f} | "
+                     f"{a_b if a_b else '-'} | {ratio} |")
+    lines.append("")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def stats_summary(stats_dir, bench_json, out, command):
+    """Markdown summary of rocprofv3 --kernel-trace --stats (kernel_stats.csv),
+    with bench.py's own per-kernel event averages of the same run beside it."""
+    import csv
+
+    with open(find_file(stats_dir, "kernel_stats.csv")) as fh:
+        rows = list(csv.DictReader(fh))
+    kinds = {}
+    lines = ["# rocprofv3 kernel statistics", "", "```"] + command + ["```", "",
+             "| kernel | calls | total us | average us | % |", "|---|---:|---:|---:|---:|"]
+    for row in rows[:16]:
+        lines.append(f"| `{row['Name'][:80]}` | {row['Calls']} | "
+                     f"{float(row['TotalDurationNs']) / 1e3:.1f} | {float(row['AverageNs']) / 1e3:.2f} | "
+                     f"{float(row['Percentage']):.1f} |")
+    for row in rows:
+        k = kernel_kind(row["Name"])
+        if k:
+            c, t = kinds.get(k, (0, 0.0))
+            kinds[k] = (c + int(row["Calls"]), t + float(row["TotalDurationNs"]))
+    ev = {}
+    if bench_json:
+        with open(bench_json) as fh:
+            for ln in fh:
+                if ln.startswith("{"):
+                    ev = json.loads(ln)["kernels"]
+    lines += ["", "Per kernel kind: rocprofv3 average per dispatch against bench.py's HIP-event "
+              "average per launch in the profiled pass (an `env` launch in bench.py covers the "
+              "trie levels one core update needs, so only its total is comparable).", "",
+              "| kind | rocprofv3 dispatches | rocprofv3 avg us | bench.py launches | bench.py avg us |",
+              "|---|---:|---:|---:|---:|"]
+    for kind, _ in KIND_PATTERNS:
+        if kind in kinds:
+            c, t = kinds[kind]
+            e = ev.get(kind, {})
+            lines.append(f"| `{kind}` | {c} | {t / c / 1e3:.2f} | {e.get('launches', '-')} | "
+                         f"{e.get('avg_us', '-')} |")
+    lines.append("")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,7 +327,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarize two rocprofv3 --pmc runs instead of benchmarking")
+    ap.add_argument("--stats-summary", metavar="STATS_DIR",
+                    help="summarize a rocprofv3 --kernel-trace --stats run instead of benchmarking")
+    ap.add_argument("--bench-json", help="bench output of the profiled run (for the summaries)")
+    ap.add_argument("--out", help="summary file to write")
+    ap.add_argument("--command", action="append", default=[],
+                    help="command line that produced the profile (repeatable, for the summary)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.calib_copy_mib or 256,
+                    args.bench_json, args.out, args.command)
+        return
+    if args.stats_summary:
+        stats_summary(args.stats_summary, args.bench_json, args.out, args.command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design note only)"}))
@@ -143,6 +359,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_stream(torch.cuda.Stream(device=dev))  # default priority
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = make_workload(args.workload)
     print(f"# workload {w.name}: n={w.n} L={w.L} r={w.r} nnz={w.nnz}", file=sys.stderr, flush=True)
     rows_d = torch.as_tensor(w.rows, dtype=torch.int32, device=dev)
@@ -172,29 +395,38 @@ def main():
     value = w.nnz * args.steps / secs
     ms_per_step = 1e3 * secs / args.steps
 
-    # roofline of the dominant kernel (largest summed event time)
+    # roofline of the dominant kernel (largest summed event time): its
+    # algorithmic bytes and flops against HBM and the ALU peak of its
+    # arithmetic; the bound is whichever of the two takes longer
     stats = [bfc.core_stats(prob, p) for p in range(w.L + 2)]
-    flops_per_sweep = {
-        "inner_gram": sum(inner_gram_flops(stats[p], w.nnz, w.r) for p in range(1, w.L + 1)),
-        "outer": 2 * outer_flops(w.nnz, w.r),
-        "env": env_flops(bfc.env_nodes(prob), w.r),
-    }
-    dom = max(flops_per_sweep, key=lambda k: kern[k][0])  # largest among the kernels with a flop model
+    cbytes = 8 if args.precision == "c64" else 16
+    models = kernel_models(stats, w, cbytes, bfc.env_nodes(prob))
+    dom = max(models, key=lambda k: kern[k][0])
     dom_ms, dom_launches = kern[dom]
-    work = flops_per_sweep[dom] * args.steps
-    achieved = work / (dom_ms * 1e-3) / 1e12
-    peak = PEAKS["fp32_TFs"] if args.precision == "c64" else PEAKS["fp64_TFs"]
+    dbytes, dflops = models[dom]
+    alu_peak = PEAKS["fp64_TFs"] if (dom == "inner_solve" or args.precision == "c128") \
+        else PEAKS["fp32_TFs"]
+    t_hbm = dbytes / (PEAKS["hbm_GBs"] * 1e9)
+    t_alu = dflops / (alu_peak * 1e12)
+    per_launch = max(dom_launches // args.steps, 1)
+    secs_dom = dom_ms * 1e-3 / args.steps  # per sweep
+    if t_hbm >= t_alu:
+        achieved, peak, unit, bound = dbytes / secs_dom / 1e9, PEAKS["hbm_GBs"], "GB/s", "hbm"
+    else:
+        achieved, peak, unit, bound = dflops / secs_dom / 1e12, alu_peak, "TFLOP/s", "alu"
+    traffic = stored_traffic(w.name, args.precision, dom)
     roofline = {
-        "bound": "alu",
+        "bound": bound,
         "kernel": dom,
         "achieved": round(achieved, 4),
         "peak": peak,
-        "unit": "TFLOP/s",
+        "unit": unit,
         "frac": round(achieved / peak, 5),
-        "traffic": None,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": round(dbytes / per_launch),
+        "algorithmic_flops_per_launch": round(dflops / per_launch),
         "avg_launch_us": round(1e3 * dom_ms / max(dom_launches, 1), 3),
         "launches": dom_launches,
-        "flops_per_sweep": flops_per_sweep[dom],
     }
     kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / max(v[1], 1), 3)} for k, v in kern.items()}
@@ -221,6 +453,8 @@ def main():
         "timing": {"events_ms_per_step": round(1e3 * ev_secs / args.steps, 4),
                    "profiled_ms_per_step": round(1e3 * psecs / args.steps, 4),
                    "sweep_launch": "captured HIP graph"},
+        "algorithmic_bytes_per_launch": {
+            k: round(v[0] / max(kern[k][1] // args.steps, 1)) for k, v in models.items()},
         "init_s": round(init_s, 4),
         "train_rel_err_after_timed": train_err,
     }
