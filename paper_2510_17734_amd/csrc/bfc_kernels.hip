@@ -261,8 +261,12 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
     const cx<T>* vals, const int32_t* sub_off, const WorkItem* items, T* partials) {
   typedef InnerGeom<R> G;
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[64 * G::LDW];
-  __shared__ T Bs[64 * G::LDW];
+  // A batch of 64 subgroups (one per lane) is staged through LDS in PH
+  // phases of 64/PH rows: at r <= 6 two phases halve the LDS a wavefront
+  // holds, so twice as many wavefronts fit on a CU
+  constexpr int PH = (R <= 6 && sizeof(T) == 4) ? 2 : 1, RP = 64 / PH;
+  __shared__ T As[RP * G::LDW];
+  __shared__ T Bs[RP * G::LDW];
   const int lane = threadIdx.x;
   const int item = xcd_swizzle(blockIdx.x, gridDim.x);
   const WorkItem it = items[item];
@@ -274,22 +278,19 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
 
   for (int base = it.sub0; base < it.sub1; base += 64) {
     const int s = base + lane;
-    T* arow = As + lane * G::LDW;
-    T* brow = Bs + lane * G::LDW;
+    const bool live = s < it.sub1;
+    T sum[G::D];
+    T yx[R], yy[R];
+    cx<T> shared_env[R];
 #pragma unroll
-    for (int k = 0; k < G::WP; ++k) {
-      arow[k] = T(0);
-      brow[k] = T(0);
+    for (int k = 0; k < G::D; ++k) sum[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      yx[k] = yy[k] = T(0);
+      shared_env[k] = cx<T>{T(0), T(0)};
     }
-    if (s < it.sub1) {
+    if (live) {
       const int e0 = sub_off[s], e1 = sub_off[s + 1];
-      T sum[G::D];
-      T yx[R], yy[R];
-#pragma unroll
-      for (int k = 0; k < G::D; ++k) sum[k] = T(0);
-#pragma unroll
-      for (int k = 0; k < R; ++k) yx[k] = yy[k] = T(0);
-      cx<T> shared_env[R];
       // the subgroup shares its row (left environment) or its column (right)
       if (BYROW)
         load_env<T, R>(lenv, lidx[e0], shared_env);
@@ -317,58 +318,70 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
           yy[k] = h.y;
         }
       }
-      T tmp[G::D];
+    }
+    T tmp[G::D];
 #pragma unroll
-      for (int k = 0; k < G::D; ++k) tmp[k] = T(0);
-      herm_acc<T, R>(tmp, shared_env);
-      if (BYROW) {
-        // A = [Rl | Re l | Im l], B = [sum Rrho | Re y | Im y], y = sum conj(rho) t
+    for (int k = 0; k < G::D; ++k) tmp[k] = T(0);
+    herm_acc<T, R>(tmp, shared_env);
 #pragma unroll
-        for (int k = 0; k < G::D; ++k) {
-          arow[k] = tmp[k];
-          brow[k] = sum[k];
+    for (int ph = 0; ph < PH; ++ph) {
+      if (lane / RP == ph) {
+        T* arow = As + (lane % RP) * G::LDW;
+        T* brow = Bs + (lane % RP) * G::LDW;
+        if (BYROW) {
+          // A = [Rl | Re l | Im l], B = [sum Rrho | Re y | Im y], y = sum conj(rho) t
+#pragma unroll
+          for (int k = 0; k < G::D; ++k) {
+            arow[k] = tmp[k];
+            brow[k] = sum[k];
+          }
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            arow[G::D + k] = shared_env[k].x;
+            arow[G::D + R + k] = shared_env[k].y;
+            brow[G::D + k] = yx[k];
+            brow[G::D + R + k] = yy[k];
+          }
+        } else {
+          // A = [sum Rl | Re w | -Im w], B = [Rrho | Re rho | -Im rho],
+          // w = sum conj(l) t: the imaginary parts are negated so that the
+          // right-hand side reads the same way as in the row case
+#pragma unroll
+          for (int k = 0; k < G::D; ++k) {
+            arow[k] = sum[k];
+            brow[k] = tmp[k];
+          }
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            arow[G::D + k] = yx[k];
+            arow[G::D + R + k] = -yy[k];
+            brow[G::D + k] = shared_env[k].x;
+            brow[G::D + R + k] = -shared_env[k].y;
+          }
         }
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          arow[G::D + k] = shared_env[k].x;
-          arow[G::D + R + k] = shared_env[k].y;
-          brow[G::D + k] = yx[k];
-          brow[G::D + R + k] = yy[k];
-        }
-      } else {
-        // A = [sum Rl | Re w | -Im w], B = [Rrho | Re rho | -Im rho],
-        // w = sum conj(l) t: the imaginary parts are negated so that the
-        // right-hand side reads the same way as in the row case
-#pragma unroll
-        for (int k = 0; k < G::D; ++k) {
-          arow[k] = sum[k];
-          brow[k] = tmp[k];
-        }
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          arow[G::D + k] = yx[k];
-          arow[G::D + R + k] = -yy[k];
-          brow[G::D + k] = shared_env[k].x;
-          brow[G::D + R + k] = -shared_env[k].y;
+        for (int k = G::W; k < G::WP; ++k) {
+          arow[k] = T(0);
+          brow[k] = T(0);
         }
       }
-    }
-    __syncthreads();
+      __syncthreads();
 #pragma unroll 4
-    for (int kk = 0; kk < 64; kk += 4) {
-      const int g = kk + (lane >> 4);
-      const int col = lane & 15;
-      T xa[G::NB], yb[G::NB];
+      for (int kk = 0; kk < RP; kk += 4) {
+        const int g = kk + (lane >> 4);
+        const int col = lane & 15;
+        T xa[G::NB], yb[G::NB];
 #pragma unroll
-      for (int x = 0; x < G::NB; ++x) xa[x] = As[g * G::LDW + x * 16 + col];
+        for (int x = 0; x < G::NB; ++x) xa[x] = As[g * G::LDW + x * 16 + col];
 #pragma unroll
-      for (int y = 0; y < G::NB; ++y) yb[y] = Bs[g * G::LDW + y * 16 + col];
+        for (int y = 0; y < G::NB; ++y) yb[y] = Bs[g * G::LDW + y * 16 + col];
 #pragma unroll
-      for (int x = 0; x < G::NB; ++x)
+        for (int x = 0; x < G::NB; ++x)
 #pragma unroll
-        for (int y = 0; y < G::NB; ++y) acc[x][y] = Mfma<T>::step(xa[x], yb[y], acc[x][y]);
+          for (int y = 0; y < G::NB; ++y) acc[x][y] = Mfma<T>::step(xa[x], yb[y], acc[x][y]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   T* out = partials + (int64_t)item * G::WP * G::WP;
 #pragma unroll
