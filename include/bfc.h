@@ -74,10 +74,12 @@ typedef int32_t bfc_status;
 /* arithmetic modes */
 #define BFC_C128 0        /* complex128 cores and contractions, FP64 Gram, FP64 solves        */
 #define BFC_C64 1         /* complex64 cores and contractions, FP32 Gram, FP64 solves          */
-#define BFC_C64_BF16GRAM 2 /* as BFC_C64 but the Gram/right-hand-side products take bf16
-                             inputs (FP32 accumulation); the FP64 solve is followed by one
-                             refinement step against the FP32 normal-equation residual
-                             recomputed from the entries                                        */
+#define BFC_C64_BF16GRAM 2 /* as BFC_C64 but the inner cores' Gram/right-hand-side products
+                             take bf16 inputs (FP32 accumulation); each inner FP64 solve is
+                             followed by one refinement step whose residual
+                             sum conj(a_e)(t_e - a_e.s) is recomputed from the entries in
+                             FP32, solved with the same factor and regularization (the outer
+                             cores' Grams stay FP32)                                            */
 
 /* regularization forms (the paper leaves the regularization unspecified) */
 #define BFC_REG_PROXIMAL 0
@@ -206,6 +208,7 @@ bfc_status bfc_solve_counters(bfc_problem* p, int32_t reset, int64_t out[2], voi
 #define BFC_KERNEL_RESIDUAL 3     /* residual norms                                       */
 #define BFC_KERNEL_PREDICT 4      /* entry reconstruction                                 */
 #define BFC_KERNEL_ENV 5          /* environment-trie levels (shared partial products)    */
+#define BFC_KERNEL_INNER_IR 6     /* BF16-Gram mode: refinement residual from the entries */
 bfc_status bfc_profile_enable(bfc_problem* p, int32_t enable);
 bfc_status bfc_profile_read(bfc_problem* p, int32_t kind, double* total_ms, int64_t* launches);
 

@@ -51,7 +51,7 @@ EXPORTS = (
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
-                "env": 5}
+                "env": 5, "inner_ir": 6}
 
 
 class BfcConfig(ctypes.Structure):

@@ -100,10 +100,6 @@ static bfc_status check_config(const bfc_config* cfg, int32_t* c_out) {
     set_error("unknown precision");
     return BFC_EINVAL;
   }
-  if (cfg->precision == BFC_C64_BF16GRAM) {
-    set_error("BFC_C64_BF16GRAM is not available in this build");
-    return BFC_EINVAL;
-  }
   if (cfg->reg_mode != BFC_REG_PROXIMAL && cfg->reg_mode != BFC_REG_RIDGE) {
     set_error("unknown regularization mode");
     return BFC_EINVAL;
@@ -183,6 +179,15 @@ bfc_status bfc_init_cores(const bfc_config* cfg, int64_t nnz, const int32_t* d_r
   if (P->max_items > 0) {
     P->partials_bytes = (size_t)P->max_items * inner_partial_bytes(P->prec, P->r);
     if ((s = dev_alloc(P, &P->partials, P->partials_bytes)) != BFC_OK) return fail(s);
+    if (P->prec == BFC_C64_BF16GRAM) {
+      const size_t d = (size_t)P->r * P->r, slices = (size_t)1 << (P->L + 1);
+      if ((s = dev_alloc(P, &P->ir_part, (size_t)P->max_items * 2 * d * sizeof(float))) != BFC_OK)
+        return fail(s);
+      if ((s = dev_alloc(P, (void**)&P->ir_lam, slices * sizeof(double))) != BFC_OK)
+        return fail(s);
+      if ((s = dev_alloc(P, &P->ir_old, slices * d * 2 * sizeof(float))) != BFC_OK)
+        return fail(s);
+    }
   }
   if (d_cores_init)
     s = launch_convert_cores(P, d_cores_init, nullptr, true, st);

@@ -114,14 +114,14 @@ struct EnvLevel {
 
 // per-kernel timing with HIP events (enabled by bfc_profile_enable)
 enum { KIND_OUTER = 0, KIND_INNER_GRAM = 1, KIND_INNER_SOLVE = 2, KIND_RESIDUAL = 3,
-       KIND_PREDICT = 4, KIND_ENV = 5, KIND_COUNT = 6 };
+       KIND_PREDICT = 4, KIND_ENV = 5, KIND_INNER_IR = 6, KIND_COUNT = 7 };
 
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KIND_COUNT];
-  double total_ms[KIND_COUNT] = {0, 0, 0, 0, 0, 0};
-  int64_t launches[KIND_COUNT] = {0, 0, 0, 0, 0, 0};
+  double total_ms[KIND_COUNT] = {};
+  int64_t launches[KIND_COUNT] = {};
   hipEvent_t take();
 };
 
@@ -151,6 +151,11 @@ struct Problem {
   void* partials = nullptr;          // inner Gram partial sums
   size_t partials_bytes = 0;
   int32_t* flags = nullptr;          // [0] solve failures since last report
+  // refinement of the BF16-Gram solves: per-item partial residual vectors,
+  // and per slice the regularization used and the slice before the update
+  void* ir_part = nullptr;
+  double* ir_lam = nullptr;
+  void* ir_old = nullptr;
   double* red = nullptr;             // residual reduction scratch
   size_t red_len = 0;
   double* red_host = nullptr;        // pinned, 2 doubles

@@ -255,6 +255,82 @@ struct InnerGeom {
   static constexpr int LDW = WP + 1;  // padded LDS row
 };
 
+// The A and B rows of one subgroup (entries e0..e1 of one slice sharing a row
+// when BYROW, else a column), in the Hermitian real coordinates described
+// above; live = false gives zero rows.  Row case: A = [Rl | Re l | Im l],
+// B = [sum Rrho | Re y | Im y], y = sum conj(rho) t.  Column case:
+// A = [sum Rl | Re w | -Im w], B = [Rrho | Re rho | -Im rho], w = sum conj(l) t:
+// the imaginary parts are negated so that the right-hand side reads the same
+// way as in the row case.
+template <typename T, int R, int BYROW>
+__device__ __attribute__((always_inline)) inline void subgroup_rows(
+    bool live, int e0, int e1, const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv,
+    const int32_t* ridx, const cx<T>* vals, T (&arow)[InnerGeom<R>::W],
+    T (&brow)[InnerGeom<R>::W]) {
+  constexpr int D = R * R;
+  T sum[D];
+  T yx[R], yy[R];
+  cx<T> shared_env[R];
+#pragma unroll
+  for (int k = 0; k < D; ++k) sum[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    yx[k] = yy[k] = T(0);
+    shared_env[k] = cx<T>{T(0), T(0)};
+  }
+  if (live) {
+    if (BYROW)
+      load_env<T, R>(lenv, lidx[e0], shared_env);
+    else
+      load_env<T, R>(renv, ridx[e0], shared_env);
+    // a subgroup holds at most kSubgroup entries: issue every index load,
+    // then every vector load, then compute
+    const int32_t* eidx = BYROW ? ridx : lidx;
+    const cx<T>* esrc = BYROW ? renv : lenv;
+    int id[kSubgroup];
+#pragma unroll
+    for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < kSubgroup; ++q) {
+      if (id[q] < 0) continue;
+      const cx<T> t = vals[e0 + q];
+      cx<T> v[R];
+      load_env<T, R>(esrc, id[q], v);
+      herm_acc<T, R>(sum, v);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        cx<T> h = {yx[k], yy[k]};
+        cfma_conj(h, v[k], t);
+        yx[k] = h.x;
+        yy[k] = h.y;
+      }
+    }
+  }
+  T tmp[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) tmp[k] = T(0);
+  herm_acc<T, R>(tmp, shared_env);
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    arow[k] = BYROW ? tmp[k] : sum[k];
+    brow[k] = BYROW ? sum[k] : tmp[k];
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (BYROW) {
+      arow[D + k] = shared_env[k].x;
+      arow[D + R + k] = shared_env[k].y;
+      brow[D + k] = yx[k];
+      brow[D + R + k] = yy[k];
+    } else {
+      arow[D + k] = yx[k];
+      arow[D + R + k] = -yy[k];
+      brow[D + k] = shared_env[k].x;
+      brow[D + R + k] = -shared_env[k].y;
+    }
+  }
+}
+
 template <typename T, int R, int BYROW>
 __global__ __launch_bounds__(64) void inner_gram_kernel(
     const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv, const int32_t* ridx,
@@ -279,85 +355,22 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
   for (int base = it.sub0; base < it.sub1; base += 64) {
     const int s = base + lane;
     const bool live = s < it.sub1;
-    T sum[G::D];
-    T yx[R], yy[R];
-    cx<T> shared_env[R];
-#pragma unroll
-    for (int k = 0; k < G::D; ++k) sum[k] = T(0);
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      yx[k] = yy[k] = T(0);
-      shared_env[k] = cx<T>{T(0), T(0)};
-    }
+    int e0 = 0, e1 = 0;
     if (live) {
-      const int e0 = sub_off[s], e1 = sub_off[s + 1];
-      // the subgroup shares its row (left environment) or its column (right)
-      if (BYROW)
-        load_env<T, R>(lenv, lidx[e0], shared_env);
-      else
-        load_env<T, R>(renv, ridx[e0], shared_env);
-      // a subgroup holds at most kSubgroup entries: issue every index load,
-      // then every vector load, then compute
-      const int32_t* eidx = BYROW ? ridx : lidx;
-      const cx<T>* esrc = BYROW ? renv : lenv;
-      int id[kSubgroup];
-#pragma unroll
-      for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
-#pragma unroll
-      for (int q = 0; q < kSubgroup; ++q) {
-        if (id[q] < 0) continue;
-        const cx<T> t = vals[e0 + q];
-        cx<T> v[R];
-        load_env<T, R>(esrc, id[q], v);
-        herm_acc<T, R>(sum, v);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          cx<T> h = {yx[k], yy[k]};
-          cfma_conj(h, v[k], t);
-          yx[k] = h.x;
-          yy[k] = h.y;
-        }
-      }
+      e0 = sub_off[s];
+      e1 = sub_off[s + 1];
     }
-    T tmp[G::D];
-#pragma unroll
-    for (int k = 0; k < G::D; ++k) tmp[k] = T(0);
-    herm_acc<T, R>(tmp, shared_env);
+    T a[G::W], b[G::W];
+    subgroup_rows<T, R, BYROW>(live, e0, e1, lenv, lidx, renv, ridx, vals, a, b);
 #pragma unroll
     for (int ph = 0; ph < PH; ++ph) {
       if (lane / RP == ph) {
         T* arow = As + (lane % RP) * G::LDW;
         T* brow = Bs + (lane % RP) * G::LDW;
-        if (BYROW) {
-          // A = [Rl | Re l | Im l], B = [sum Rrho | Re y | Im y], y = sum conj(rho) t
 #pragma unroll
-          for (int k = 0; k < G::D; ++k) {
-            arow[k] = tmp[k];
-            brow[k] = sum[k];
-          }
-#pragma unroll
-          for (int k = 0; k < R; ++k) {
-            arow[G::D + k] = shared_env[k].x;
-            arow[G::D + R + k] = shared_env[k].y;
-            brow[G::D + k] = yx[k];
-            brow[G::D + R + k] = yy[k];
-          }
-        } else {
-          // A = [sum Rl | Re w | -Im w], B = [Rrho | Re rho | -Im rho],
-          // w = sum conj(l) t: the imaginary parts are negated so that the
-          // right-hand side reads the same way as in the row case
-#pragma unroll
-          for (int k = 0; k < G::D; ++k) {
-            arow[k] = sum[k];
-            brow[k] = tmp[k];
-          }
-#pragma unroll
-          for (int k = 0; k < R; ++k) {
-            arow[G::D + k] = yx[k];
-            arow[G::D + R + k] = -yy[k];
-            brow[G::D + k] = shared_env[k].x;
-            brow[G::D + R + k] = -shared_env[k].y;
-          }
+        for (int k = 0; k < G::W; ++k) {
+          arow[k] = a[k];
+          brow[k] = b[k];
         }
 #pragma unroll
         for (int k = G::W; k < G::WP; ++k) {
@@ -396,6 +409,182 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
       }
 }
 
+// BF16-input variant (precision BFC_C64_BF16GRAM): the same A/B rows are
+// rounded to bfloat16 and multiplied by the 16x16x32 BF16 MFMA with FP32
+// accumulation.  The rows are staged transposed (coordinate-major, one
+// column per subgroup), so each lane reads its eight consecutive subgroups of
+// one coordinate as one 16-byte vector: lane l holds A[l%16][8(l/16)+t],
+// the layout of the instruction's A and B operands.  The output layout equals
+// the FP32 instruction's, so the partial products keep their format.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// BF16-Gram mode: regularization floor of the inner solves and refinement
+// steps.  A bf16-formed Gram differs from the exact one by up to ~2^-8 of its
+// entries; refinement with that factor contracts only where lam dominates the
+// difference.  At a floor of 2^-8 every update refines to within ~1e-5 of the
+// regularized optimum but the damping slows the sweeps; at 2^-12 one step
+// leaves updates within ~1e-2 of it and the sweeps converge nearly as fast as
+// with the FP32 Gram (measured on the Green's-function workloads).
+constexpr double kBf16RegFloor = 0x1p-12;
+constexpr int kBf16IrSteps = 1;
+constexpr int kBfLd = 64 + 8;  // subgroups per staged coordinate row, padded
+
+template <int R, int BYROW>
+__global__ __launch_bounds__(64) void inner_gram_bf16_kernel(
+    const cx<float>* lenv, const int32_t* lidx, const cx<float>* renv, const int32_t* ridx,
+    const cx<float>* vals, const int32_t* sub_off, const WorkItem* items, float* partials) {
+  typedef InnerGeom<R> G;
+  typedef Mfma<float>::acc_t acc_t;
+  __shared__ __attribute__((aligned(16))) __bf16 At[G::WP * kBfLd];
+  __shared__ __attribute__((aligned(16))) __bf16 Bt[G::WP * kBfLd];
+  const int lane = threadIdx.x;
+  const int item = xcd_swizzle(blockIdx.x, gridDim.x);
+  const WorkItem it = items[item];
+  acc_t acc[G::NB][G::NB];
+#pragma unroll
+  for (int x = 0; x < G::NB; ++x)
+#pragma unroll
+    for (int y = 0; y < G::NB; ++y) acc[x][y] = acc_t{0.f, 0.f, 0.f, 0.f};
+
+  for (int base = it.sub0; base < it.sub1; base += 64) {
+    const int s = base + lane;
+    const bool live = s < it.sub1;
+    int e0 = 0, e1 = 0;
+    if (live) {
+      e0 = sub_off[s];
+      e1 = sub_off[s + 1];
+    }
+    float a[G::W], b[G::W];
+    subgroup_rows<float, R, BYROW>(live, e0, e1, lenv, lidx, renv, ridx, vals, a, b);
+#pragma unroll
+    for (int k = 0; k < G::W; ++k) {
+      At[k * kBfLd + lane] = (__bf16)a[k];
+      Bt[k * kBfLd + lane] = (__bf16)b[k];
+    }
+#pragma unroll
+    for (int k = G::W; k < G::WP; ++k) {
+      At[k * kBfLd + lane] = (__bf16)0.f;
+      Bt[k * kBfLd + lane] = (__bf16)0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const int off = (lane & 15) * kBfLd + kb * 32 + 8 * (lane >> 4);
+      bf16x8 xa[G::NB], yb[G::NB];
+#pragma unroll
+      for (int x = 0; x < G::NB; ++x) xa[x] = *(const bf16x8*)(At + x * 16 * kBfLd + off);
+#pragma unroll
+      for (int y = 0; y < G::NB; ++y) yb[y] = *(const bf16x8*)(Bt + y * 16 * kBfLd + off);
+#pragma unroll
+      for (int x = 0; x < G::NB; ++x)
+#pragma unroll
+        for (int y = 0; y < G::NB; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[x], yb[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* out = partials + (int64_t)item * G::WP * G::WP;
+#pragma unroll
+  for (int x = 0; x < G::NB; ++x)
+#pragma unroll
+    for (int y = 0; y < G::NB; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = x * 16 + Mfma<float>::out_row(lane, v);
+        const int col = y * 16 + (lane & 15);
+        out[row * G::WP + col] = acc[x][y][v];
+      }
+}
+
+// Refinement residual of the BF16-Gram solves, recomputed from the entries in
+// FP32: per work item, g = sum_e conj(a_e) (t_e - a_e . s0) over its
+// subgroups, with s0 the slice just solved for (a_e = l (x) rho, so a_e . s0 =
+// l^T S0 rho).  Row groups share l: v = l^T S0 once, then per entry
+// res = t - v . rho and w += conj(rho) res, and g += conj(l) (x) w.  Column
+// groups share rho: u = S0 rho, res = t - l . u, w += conj(l) res,
+// g += w (x) conj(rho).  Output: ir_part[item][2 d] (re, im interleaved),
+// the wavefront's lanes summed in a fixed order.
+template <int R, int BYROW>
+__global__ __launch_bounds__(64) void inner_ir_kernel(
+    const cx<float>* lenv, const int32_t* lidx, const cx<float>* renv, const int32_t* ridx,
+    const cx<float>* vals, const int32_t* sub_off, const WorkItem* items, const cx<float>* slices,
+    float* ir_part) {
+  constexpr int D = R * R, LDR = 2 * D + 1;
+  __shared__ float red[64 * LDR];
+  __shared__ cx<float> S0[D];
+  const int lane = threadIdx.x;
+  const int item = xcd_swizzle(blockIdx.x, gridDim.x);
+  const WorkItem it = items[item];
+  for (int k = lane; k < D; k += 64) S0[k] = slices[(int64_t)it.tile * D + k];
+  __syncthreads();
+  float gx[D], gy[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) gx[k] = gy[k] = 0.f;
+  for (int base = it.sub0; base < it.sub1; base += 64) {
+    const int s = base + lane;
+    if (s >= it.sub1) continue;
+    const int e0 = sub_off[s], e1 = sub_off[s + 1];
+    cx<float> sh[R], m[R], w[R];
+    if (BYROW)
+      load_env<float, R>(lenv, lidx[e0], sh);
+    else
+      load_env<float, R>(renv, ridx[e0], sh);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      m[k] = cx<float>{0.f, 0.f};
+      w[k] = cx<float>{0.f, 0.f};
+    }
+    // BYROW: m_b = sum_a l_a S0[a][b]; else m_a = sum_b S0[a][b] rho_b
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        if (BYROW)
+          cfma(m[b], sh[a], S0[a * R + b]);
+        else
+          cfma(m[a], S0[a * R + b], sh[b]);
+      }
+    const int32_t* eidx = BYROW ? ridx : lidx;
+    const cx<float>* esrc = BYROW ? renv : lenv;
+    int id[kSubgroup];
+#pragma unroll
+    for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < kSubgroup; ++q) {
+      if (id[q] < 0) continue;
+      const cx<float> t = vals[e0 + q];
+      cx<float> v[R];
+      load_env<float, R>(esrc, id[q], v);
+      cx<float> x = {0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < R; ++k) cfma(x, m[k], v[k]);
+      const cx<float> res = {t.x - x.x, t.y - x.y};
+#pragma unroll
+      for (int k = 0; k < R; ++k) cfma_conj(w[k], v[k], res);  // w += conj(v) res
+    }
+    // g[a*R+b] += conj(l_a) w_b (row groups) or w_a conj(rho_b) (column groups)
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        const cx<float> p = BYROW ? sh[a] : sh[b];
+        const cx<float> q = BYROW ? w[b] : w[a];
+        gx[a * R + b] += p.x * q.x + p.y * q.y;  // conj(p) q
+        gy[a * R + b] += p.x * q.y - p.y * q.x;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    red[lane * LDR + 2 * k] = gx[k];
+    red[lane * LDR + 2 * k + 1] = gy[k];
+  }
+  __syncthreads();
+  for (int k = lane; k < 2 * D; k += 64) {
+    float acc = 0.f;
+    for (int l = 0; l < 64; ++l) acc += red[l * LDR + k];
+    ir_part[(int64_t)item * 2 * D + k] = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // inner cores: per-slice sum of partials, FP64 Hermitian solve (one workgroup)
 // ---------------------------------------------------------------------------
@@ -419,10 +608,17 @@ constexpr int kSolveThreads = 256;
 // One workgroup per slice: sum the slice's partial products (S), assemble the
 // Hermitian system (K, h), factor K + lam I bordered by the right-hand side
 // h + lam s_old (regularization ladder), back-substitute, write the slice.
+// pass 0: the one solve of the FP64 / FP32-Gram modes.  pass 1: the first
+// solve of the BF16-Gram mode, which also keeps the slice's regularization
+// (ir_lam, negative when the slice is kept) and its old values (ir_old).
+// pass 2: the refinement, (K + lam I) delta = g + lam (s_old - s0) (ridge:
+// g - lam s0) with the same lam and g the entries' residual vector (ir_part,
+// per work item); the slice becomes s0 + delta.
 template <typename T, int R>
 __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2))) void inner_solve_kernel(
     cx<T>* slices, const T* partials, const int32_t* tile_items, double reg_rel,
-    double reg_floor, int prox, int32_t* flags) {
+    double reg_floor, int prox, int32_t* flags, int pass, double* ir_lam, cx<T>* ir_old,
+    const float* ir_part) {
   typedef SolveGeom<R> G;
   constexpr int D = G::D, WP = G::WP, LD = G::LD, NT = kSolveThreads;
   __shared__ double2 K[D * LD];
@@ -502,10 +698,30 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
   double lam = fmax(reg_rel, D * reg_floor) * tau;
   cx<T>* slice = slices + (int64_t)tile * D;
   double2 old = make_double2(0.0, 0.0);
-  if (prox && tid < D) old = make_double2((double)slice[tid].x, (double)slice[tid].y);
+  if ((prox || pass == 2) && tid < D) old = make_double2((double)slice[tid].x, (double)slice[tid].y);
+  double2 rhs = h;  // right-hand side of the bordered factorization
+  if (pass == 2) {
+    lam = ir_lam[tile];
+    if (!(lam >= 0.0)) return;  // the first pass kept this slice
+    if (tid < D) {
+      // old holds s0 here; g from the work items in a fixed order
+      double gx = 0.0, gy = 0.0;
+      for (int it = it0; it < it1; ++it) {
+        gx += (double)ir_part[(int64_t)it * 2 * D + 2 * tid];
+        gy += (double)ir_part[(int64_t)it * 2 * D + 2 * tid + 1];
+      }
+      const cx<T> so = ir_old[(int64_t)tile * D + tid];
+      // residual of the regularized system at s0: g + lam (s_old - s0)
+      // (proximal) or g - lam s0 (ridge)
+      const double ox = prox ? (double)so.x : 0.0, oy = prox ? (double)so.y : 0.0;
+      rhs = make_double2(gx + lam * (ox - old.x), gy + lam * (oy - old.y));
+    }
+  } else if (pass == 1 && tid < D) {
+    ir_old[(int64_t)tile * D + tid] = slice[tid];
+  }
   bool ok = false;
   int attempt = 0;
-  for (; attempt < 4; ++attempt) {
+  for (; attempt < (pass == 2 ? 1 : 4); ++attempt) {
     if (attempt > 0) {
       if (!(lam > 0.0)) break;
       lam = fmax(100.0 * lam, D * unit * tau);
@@ -515,17 +731,29 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
       if (k % LD == k / LD) v.x += lam;
       M[k] = v;
     }
-    if (tid < D)  // border row: conj(h + lam old)
-      M[D * LD + tid] = make_double2(h.x + lam * old.x, -(h.y + lam * old.y));
+    if (tid < D) {  // border row: conj(right-hand side)
+      double2 b = rhs;
+      if (pass != 2 && prox) {
+        b.x += lam * old.x;
+        b.y += lam * old.y;
+      }
+      M[D * LD + tid] = make_double2(b.x, -b.y);
+    }
     __syncthreads();
     ok = wg_cholesky<NT>(M, D, LD, panel, dinv, tid);
     if (ok) break;
   }
   if (!ok) {
-    if (tid == 0) atomicAdd(flags, 1);
+    if (tid == 0) {
+      atomicAdd(flags, 1);
+      if (pass == 1) ir_lam[tile] = -1.0;
+    }
     return;
   }
-  if (attempt > 0 && tid == 0) atomicAdd(flags + 1, 1);
+  if (tid == 0) {
+    if (attempt > 0) atomicAdd(flags + 1, 1);
+    if (pass == 1) ir_lam[tile] = lam;
+  }
   if (tid >= 64) return;  // one wavefront solves; no barriers below
   double2 y = make_double2(0.0, 0.0);
   if (lane < D) {
@@ -533,6 +761,10 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
     y = make_double2(t.x, -t.y);
   }
   wave_back_solve(M, dinv, D, LD, y, lane);
+  if (pass == 2) {
+    y.x += old.x;
+    y.y += old.y;
+  }
   if (lane < D) slice[lane] = {T(y.x), T(y.y)};
 }
 
@@ -715,10 +947,14 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   cx<T>* cores = (cx<T>*)P->cores;
   const CoreLayout& C = P->lay[p];
   const double reg = P->cfg.reg_rel;
-  // Gram accumulated in FP32: keep lam above its rounding level
-  const double floor_ = P->prec == BFC_C128 ? 0.0 : 0x1p-24;
-  const int prox = P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0;
+  // keep lam above the rounding level of the Gram: none for FP64, the unit
+  // roundoff of FP32 accumulation, or that of the bf16 inputs
   const int L = P->L;
+  const bool outer = p == 0 || p == L + 1;  // outer Grams are FP32 in both complex64 modes
+  const double floor_ = P->prec == BFC_C128             ? 0.0
+                        : (P->prec == BFC_C64 || outer) ? 0x1p-24
+                                                        : kBf16RegFloor;
+  const int prox = P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0;
   {
     ProfScope ps(&P->prof, KIND_ENV, st);
     BFC_TRY(ensure_right<T, R>(P, p, st));
@@ -743,24 +979,62 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
     }
     BFC_HIP_TRY(hipGetLastError());
   } else {
+    const bool bf16 = P->prec == BFC_C64_BF16GRAM;
     if (C.nitems > 0) {
       ProfScope ps(&P->prof, KIND_INNER_GRAM, st);
-      if (C.group_by_row)
-        inner_gram_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(
-            lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
-      else
-        inner_gram_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(
-            lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
+      if constexpr (std::is_same<T, float>::value) {
+        if (bf16) {
+          if (C.group_by_row)
+            inner_gram_bf16_kernel<R, 1><<<C.nitems, 64, 0, st>>>(
+                lenv, lidx, renv, ridx, (const cx<float>*)C.vals, C.sub_off, C.items,
+                (float*)P->partials);
+          else
+            inner_gram_bf16_kernel<R, 0><<<C.nitems, 64, 0, st>>>(
+                lenv, lidx, renv, ridx, (const cx<float>*)C.vals, C.sub_off, C.items,
+                (float*)P->partials);
+        }
+      }
+      if (!bf16) {
+        if (C.group_by_row)
+          inner_gram_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(
+              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
+        else
+          inner_gram_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(
+              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
+      }
       BFC_HIP_TRY(hipGetLastError());
     }
     cx<T>* slices = cores + inner_off(P->n, L, R, p);
     {
       ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
-      inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(slices, (const T*)P->partials,
-                                                         C.tile_items, reg, floor_, prox,
-                                                         P->flags);
+      inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(
+          slices, (const T*)P->partials, C.tile_items, reg, floor_, prox, P->flags, bf16 ? 1 : 0,
+          P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part);
     }
     BFC_HIP_TRY(hipGetLastError());
+    if constexpr (std::is_same<T, float>::value) {
+      for (int step = 0; bf16 && C.nitems > 0 && step < kBf16IrSteps; ++step) {
+        {
+          ProfScope ps(&P->prof, KIND_INNER_IR, st);
+          if (C.group_by_row)
+            inner_ir_kernel<R, 1><<<C.nitems, 64, 0, st>>>(
+                lenv, lidx, renv, ridx, (const cx<float>*)C.vals, C.sub_off, C.items, slices,
+                (float*)P->ir_part);
+          else
+            inner_ir_kernel<R, 0><<<C.nitems, 64, 0, st>>>(
+                lenv, lidx, renv, ridx, (const cx<float>*)C.vals, C.sub_off, C.items, slices,
+                (float*)P->ir_part);
+        }
+        BFC_HIP_TRY(hipGetLastError());
+        {
+          ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
+          inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(
+              slices, (const T*)P->partials, C.tile_items, reg, floor_, prox, P->flags, 2,
+              P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part);
+        }
+        BFC_HIP_TRY(hipGetLastError());
+      }
+    }
   }
   // core p changed: right levels below it and left levels above it are stale
   for (int q = 0; q < p && q < L; ++q) P->rlev[q].valid = false;
