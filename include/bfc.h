@@ -230,6 +230,33 @@ void bfc_destroy(bfc_problem* p);
 /* Message describing the calling thread's last error ("" if none). */
 const char* bfc_last_error(void);
 
+/*
+ * Batched sweeps of independent problems (many completion instances of uneven
+ * n, L and r advanced together).  Each problem's sweep is Alg. "ALS for
+ * Butterfly Completion" (Sec. 5.1.1) exactly as bfc_sweep runs it; the batch
+ * only shares the launches: every launch covers one kernel kind of every
+ * problem that needs it at that step of the sweep (problems of one rank per
+ * launch), and results are bit-identical to sweeping the problems one by one.
+ *
+ * bfc_batch_create: problems[0..count-1] (count >= 1, distinct, all BFC_C128
+ *   or all BFC_C64; BFC_C64_BF16GRAM is rejected with BFC_EINVAL) stay owned
+ *   by the caller and must outlive the batch.  Builds the launch plan in
+ *   device memory (synchronous).  *out receives the batch, NULL on error.
+ * bfc_batch_sweep: one sweep of every problem on hip_stream (asynchronous);
+ *   on a non-null stream the launch list is captured once into a HIP graph
+ *   and replayed.
+ * bfc_batch_residuals: out_sq[2k], out_sq[2k+1] = ||P(T - X)||^2, ||P T||^2 of
+ *   problem k over its own observed entries, FP64 (host array of 2*count;
+ *   synchronizes hip_stream).  Returns BFC_ENOTSPD, after filling out_sq,
+ *   when any problem's slices were kept since the last report.
+ * bfc_batch_destroy: releases the plan (not the problems); NULL is ignored.
+ */
+typedef struct bfc_batch bfc_batch;
+bfc_status bfc_batch_create(bfc_problem* const* problems, int32_t count, bfc_batch** out);
+bfc_status bfc_batch_sweep(bfc_batch* b, void* hip_stream);
+bfc_status bfc_batch_residuals(bfc_batch* b, double* out_sq, void* hip_stream);
+bfc_status bfc_batch_destroy(bfc_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,11 @@ does not load the library; the first call does, and fails loudly if it has
 not been built.
 """
 from .api import (  # noqa: F401
+    Batch,
     BfcError,
+    batch_create,
+    batch_residuals,
+    batch_sweep,
     Config,
     core_stats,
     profile_enable,

@@ -48,6 +48,10 @@ EXPORTS = (
     "bfc_solve_counters",
     "bfc_residual_observed",
     "bfc_use_graphs",
+    "bfc_batch_create",
+    "bfc_batch_sweep",
+    "bfc_batch_residuals",
+    "bfc_batch_destroy",
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
@@ -115,6 +119,14 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_residual_observed.restype = i32
     lib.bfc_use_graphs.argtypes = [P, i32]
     lib.bfc_use_graphs.restype = i32
+    lib.bfc_batch_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(P)]
+    lib.bfc_batch_create.restype = i32
+    lib.bfc_batch_sweep.argtypes = [P, vp]
+    lib.bfc_batch_sweep.restype = i32
+    lib.bfc_batch_residuals.argtypes = [P, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_batch_residuals.restype = i32
+    lib.bfc_batch_destroy.argtypes = [P]
+    lib.bfc_batch_destroy.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

@@ -259,3 +259,51 @@ def solve_counters(p: Problem, reset: bool = False, stream=None):
 def use_graphs(p: Problem, enable: bool = True):
     """bfc_use_graphs: replay bfc_sweep from a captured HIP graph (default on)."""
     _check(_lib.load().bfc_use_graphs(p.handle, 1 if enable else 0), "bfc_use_graphs")
+
+
+class Batch:
+    """Owns a bfc_batch handle: independent problems swept together (the
+    problems stay owned by the caller and must outlive the batch)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (ctypes.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
+        h = ctypes.c_void_p()
+        _check(_lib.load().bfc_batch_create(arr, len(self.problems), ctypes.byref(h)),
+               "bfc_batch_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch already destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _lib.load().bfc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_create(problems) -> Batch:
+    """bfc_batch_create."""
+    return Batch(problems)
+
+
+def batch_sweep(b: Batch, stream=None):
+    """bfc_batch_sweep: one sweep of every problem of the batch."""
+    _check(_lib.load().bfc_batch_sweep(b.handle, _stream(stream)), "bfc_batch_sweep")
+
+
+def batch_residuals(b: Batch, stream=None):
+    """bfc_batch_residuals: [(||P(T - X)||^2, ||P T||^2)] per problem, observed entries."""
+    k = len(b.problems)
+    out = (ctypes.c_double * (2 * k))()
+    _check(_lib.load().bfc_batch_residuals(b.handle, out, _stream(stream)), "bfc_batch_residuals")
+    return [(float(out[2 * q]), float(out[2 * q + 1])) for q in range(k)]

@@ -447,3 +447,147 @@ void bfc_destroy(bfc_problem* p) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched sweeps
+// ---------------------------------------------------------------------------
+struct bfc_batch : public bfc::Batch {};
+
+namespace {
+void free_batch(bfc_batch* B) {
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (void* p : B->allocs) (void)hipFree(p);
+  if (B->res_host) (void)hipHostFree(B->res_host);
+  delete B;
+}
+}  // namespace
+
+bfc_status bfc_batch_create(bfc_problem* const* problems, int32_t count, bfc_batch** out) {
+  if (!out) {
+    set_error("null output pointer");
+    return BFC_EINVAL;
+  }
+  *out = nullptr;
+  if (!problems || count < 1) {
+    set_error("a batch needs at least one problem");
+    return BFC_EINVAL;
+  }
+  for (int32_t k = 0; k < count; ++k) {
+    if (!problems[k]) {
+      set_error("null problem in batch");
+      return BFC_EINVAL;
+    }
+    for (int32_t q = 0; q < k; ++q)
+      if (problems[q] == problems[k]) {
+        set_error("a problem appears twice in the batch");
+        return BFC_EINVAL;
+      }
+    if (problems[k]->prec != problems[0]->prec) {
+      set_error("problems of one batch must share the arithmetic mode");
+      return BFC_EINVAL;
+    }
+  }
+  if (problems[0]->prec == BFC_C64_BF16GRAM) {
+    set_error("batched sweeps take BFC_C128 or BFC_C64 problems");
+    return BFC_EINVAL;
+  }
+  bfc_batch* B = new (std::nothrow) bfc_batch();
+  if (!B) {
+    set_error("host allocation failed");
+    return BFC_ENOMEM;
+  }
+  B->prec = problems[0]->prec;
+  for (int32_t k = 0; k < count; ++k) B->probs.push_back(problems[k]);
+  bfc_status s = BFC_OK;
+  if (hipMalloc((void**)&B->res, 2 * sizeof(double) * count) != hipSuccess ||
+      hipHostMalloc((void**)&B->res_host, 2 * sizeof(double) * count, hipHostMallocDefault) !=
+          hipSuccess) {
+    if (B->res) (void)hipFree(B->res);
+    B->res = nullptr;
+    free_batch(B);
+    set_error("batch allocation failed");
+    return BFC_ENOMEM;
+  }
+  B->allocs.push_back(B->res);
+  if ((s = build_batch_plan(B)) != BFC_OK) {
+    free_batch(B);
+    return s;
+  }
+  *out = B;
+  return BFC_OK;
+}
+
+bfc_status bfc_batch_sweep(bfc_batch* b, void* hip_stream) {
+  if (!b) {
+    set_error("null batch");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (st != nullptr) {
+    if (!b->exec) {
+      BFC_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      bfc_status s = launch_batch(b->sweep, b->prec, st);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(st, &g);
+      if (s != BFC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+      }
+      BFC_HIP_TRY(e);
+      b->graph = g;
+      BFC_HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    }
+    BFC_HIP_TRY(hipGraphLaunch(b->exec, st));
+  } else {
+    BFC_TRY(launch_batch(b->sweep, b->prec, st));
+  }
+  // as after a single sweep: every right level is stale, every left level current
+  for (bfc::Problem* P : b->probs) {
+    for (auto& E : P->rlev) E.valid = false;
+    for (size_t q = 2; q < P->llev.size(); ++q) P->llev[q].valid = true;
+  }
+  return BFC_OK;
+}
+
+bfc_status bfc_batch_residuals(bfc_batch* b, double* out_sq, void* hip_stream) {
+  if (!b || !out_sq) {
+    set_error("bad batch_residuals arguments");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t k = b->probs.size();
+  // the residuals read the last left level of every problem: bring stale ones
+  // up to date (a no-op right after a batched sweep)
+  for (bfc::Problem* P : b->probs) {
+    bool stale = false;
+    for (int q = 2; q <= P->L + 1; ++q) stale = stale || !P->llev[q].valid;
+    if (stale) BFC_TRY(launch_residual_observed(P, P->red + P->red_len, st));
+  }
+  BFC_TRY(launch_batch(b->resid, b->prec, st));
+  BFC_HIP_TRY(hipMemcpyAsync(b->res_host, b->res, 2 * sizeof(double) * k, hipMemcpyDeviceToHost,
+                             st));
+  std::vector<int32_t> nfail(k, 0);
+  for (size_t q = 0; q < k; ++q)
+    BFC_HIP_TRY(hipMemcpyAsync(&nfail[q], b->probs[q]->flags, 4, hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  for (size_t q = 0; q < 2 * k; ++q) out_sq[q] = b->res_host[q];
+  int64_t total = 0;
+  for (size_t q = 0; q < k; ++q)
+    if (nfail[q]) {
+      total += nfail[q];
+      BFC_HIP_TRY(hipMemsetAsync(b->probs[q]->flags, 0, 4, st));
+    }
+  if (total) {
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+    set_error("a regularized normal-equation matrix was not positive definite (" +
+              std::to_string(total) + " blocks kept their values)");
+    return BFC_ENOTSPD;
+  }
+  return BFC_OK;
+}
+
+bfc_status bfc_batch_destroy(bfc_batch* b) {
+  if (b) free_batch(b);
+  return BFC_OK;
+}

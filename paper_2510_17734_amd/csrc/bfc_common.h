@@ -173,6 +173,35 @@ struct Problem {
 
 bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes);
 
+// One launch of a batched sweep: a kernel kind at one rank, over tasks (one
+// per problem taking part) whose argument structs and block prefix table live
+// in device memory.
+enum { BK_ENV_RIGHT = 0, BK_ENV_LEFT = 1, BK_OUTER = 2, BK_GRAM_ROW = 3, BK_GRAM_COL = 4,
+       BK_SOLVE = 5, BK_RES = 6, BK_RES_FINAL = 7 };
+struct BatchLaunch {
+  int kind = 0, r = 0;
+  void* tasks = nullptr;        // device array of argument structs
+  int32_t* block_off = nullptr; // device, ntasks + 1
+  int ntasks = 0;
+  int64_t blocks = 0;
+};
+
+// Independent problems swept together: each launch covers the same kernel
+// kind of every problem that needs it at that step of the sweep.
+struct Batch {
+  std::vector<Problem*> probs;
+  int prec = BFC_C64;
+  std::vector<BatchLaunch> sweep;  // one sweep of every problem, in dependency order
+  std::vector<BatchLaunch> resid;  // observed-set residual norms of every problem
+  double* res = nullptr;           // device, 2 per problem
+  double* res_host = nullptr;      // pinned, 2 per problem
+  std::vector<void*> allocs;       // device memory of the plan
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+bfc_status build_batch_plan(Batch* B);
+bfc_status launch_batch(const std::vector<BatchLaunch>& plan, int prec, hipStream_t st);
+
 // geometry helpers (host)
 inline int64_t num_params(int64_t n, int L, int r) {
   return 2 * n * r + (int64_t)L * (int64_t(1) << (L + 1)) * r * r;

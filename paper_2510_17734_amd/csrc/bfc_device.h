@@ -38,6 +38,22 @@ __device__ inline int xcd_swizzle(int bid, int nblocks) {
 }
 
 // v <- the R-vector at src + idx * R
+// Work of one launch split into tasks (one per instance of a batch): a
+// batched kernel reads its task's arguments from `tasks` and its block index
+// within the task from the prefix table `block_off` (ntasks + 1 entries).
+__device__ __attribute__((always_inline)) inline int find_task(const int32_t* block_off,
+                                                               int ntasks, int b) {
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {  // last task with block_off[t] <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (block_off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename T, int R>
 __device__ inline void load_env(const cx<T>* __restrict__ src, int idx, cx<T> (&v)[R]) {
   const cx<T>* p = src + (int64_t)idx * R;

@@ -114,6 +114,37 @@ __global__ __launch_bounds__(kResThreads) void residual_final_kernel(const doubl
   }
 }
 
+// One block per task: the per-block partial norms of one problem summed in
+// the same order as residual_final_kernel.
+struct ResFinalArgs {
+  const double* partial;
+  int nblk;
+  double* out;
+};
+__global__ __launch_bounds__(kResThreads) void residual_final_batched(const ResFinalArgs* tasks) {
+  const ResFinalArgs a = tasks[blockIdx.x];
+  __shared__ double s0[kResThreads], s1[kResThreads];
+  double a0 = 0.0, a1 = 0.0;
+  for (int b = threadIdx.x; b < a.nblk; b += kResThreads) {
+    a0 += a.partial[2 * b];
+    a1 += a.partial[2 * b + 1];
+  }
+  s0[threadIdx.x] = a0;
+  s1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int off = kResThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s0[threadIdx.x] += s0[threadIdx.x + off];
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.out[0] = s0[0];
+    a.out[1] = s1[0];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Hermitian system assembly from real coordinates
 // ---------------------------------------------------------------------------
@@ -148,14 +179,36 @@ __device__ inline double2 inner_h(const double* S, int W, int row) {
 // ---------------------------------------------------------------------------
 constexpr int kOuterThreads = 256;
 
+template <typename T>
+struct OuterArgs {
+  cx<T>* fibers;
+  const cx<T>* env;
+  const int32_t* env_idx;
+  const cx<T>* vals;
+  const int32_t* blk_off;
+  int nblocks;
+  double reg_rel;
+  double reg_floor;
+  int prox;
+  int32_t* flags;
+};
+
 template <typename T, int R>
-__global__ __launch_bounds__(kOuterThreads) void outer_update_kernel(
-    cx<T>* fibers, const cx<T>* env, const int32_t* env_idx, const cx<T>* vals,
-    const int32_t* blk_off, int nblocks, double reg_rel, double reg_floor, int prox,
-    int32_t* flags) {
+__device__ __attribute__((always_inline)) inline void outer_update_body(const OuterArgs<T>& A, int blk) {
+  cx<T>* fibers = A.fibers;
+  const cx<T>* env = A.env;
+  const int32_t* env_idx = A.env_idx;
+  const cx<T>* vals = A.vals;
+  const int32_t* blk_off = A.blk_off;
+  int nblocks = A.nblocks;
+  double reg_rel = A.reg_rel;
+  double reg_floor = A.reg_floor;
+  int prox = A.prox;
+  int32_t* flags = A.flags;
+
   constexpr int D = R * R;
   const int sub = threadIdx.x & 15;
-  const int b = (xcd_swizzle(blockIdx.x, gridDim.x) * kOuterThreads + threadIdx.x) >> 4;
+  const int b = (blk * kOuterThreads + threadIdx.x) >> 4;
   int e0 = 0, e1 = 0;
   if (b < nblocks) {
     e0 = blk_off[b];
@@ -242,6 +295,20 @@ __global__ __launch_bounds__(kOuterThreads) void outer_update_kernel(
 #pragma unroll
   for (int k = 0; k < R; ++k) fiber[k] = {T(sol[k].x), T(sol[k].y)};
 }
+
+template <typename T, int R>
+__global__ __launch_bounds__(kOuterThreads) void outer_update_kernel(OuterArgs<T> A) {
+  outer_update_body<T, R>(A, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kOuterThreads) void outer_update_kernel_batched(const OuterArgs<T>* tasks, const int32_t* block_off,
+    int ntasks) {
+  const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int t = find_task(block_off, ntasks, b);
+  outer_update_body<T, R>(tasks[t], b - block_off[t]);
+}
+
 
 // ---------------------------------------------------------------------------
 // inner cores: Gram/RHS partial products per work item (one wavefront)
@@ -331,10 +398,29 @@ __device__ __attribute__((always_inline)) inline void subgroup_rows(
   }
 }
 
+template <typename T>
+struct GramArgs {
+  const cx<T>* lenv;
+  const int32_t* lidx;
+  const cx<T>* renv;
+  const int32_t* ridx;
+  const cx<T>* vals;
+  const int32_t* sub_off;
+  const WorkItem* items;
+  T* partials;
+};
+
 template <typename T, int R, int BYROW>
-__global__ __launch_bounds__(64) void inner_gram_kernel(
-    const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv, const int32_t* ridx,
-    const cx<T>* vals, const int32_t* sub_off, const WorkItem* items, T* partials) {
+__device__ __attribute__((always_inline)) inline void inner_gram_body(const GramArgs<T>& A, int blk) {
+  const cx<T>* lenv = A.lenv;
+  const int32_t* lidx = A.lidx;
+  const cx<T>* renv = A.renv;
+  const int32_t* ridx = A.ridx;
+  const cx<T>* vals = A.vals;
+  const int32_t* sub_off = A.sub_off;
+  const WorkItem* items = A.items;
+  T* partials = A.partials;
+
   typedef InnerGeom<R> G;
   typedef typename Mfma<T>::acc_t acc_t;
   // A batch of 64 subgroups (one per lane) is staged through LDS in PH
@@ -344,7 +430,7 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
   __shared__ T As[RP * G::LDW];
   __shared__ T Bs[RP * G::LDW];
   const int lane = threadIdx.x;
-  const int item = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int item = blk;
   const WorkItem it = items[item];
   acc_t acc[G::NB][G::NB];
 #pragma unroll
@@ -408,6 +494,20 @@ __global__ __launch_bounds__(64) void inner_gram_kernel(
         out[row * G::WP + col] = acc[x][y][v];
       }
 }
+
+template <typename T, int R, int BYROW>
+__global__ __launch_bounds__(64) void inner_gram_kernel(GramArgs<T> A) {
+  inner_gram_body<T, R, BYROW>(A, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R, int BYROW>
+__global__ __launch_bounds__(64) void inner_gram_kernel_batched(const GramArgs<T>* tasks, const int32_t* block_off,
+    int ntasks) {
+  const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int t = find_task(block_off, ntasks, b);
+  inner_gram_body<T, R, BYROW>(tasks[t], b - block_off[t]);
+}
+
 
 // BF16-input variant (precision BFC_C64_BF16GRAM): the same A/B rows are
 // rounded to bfloat16 and multiplied by the 16x16x32 BF16 MFMA with FP32
@@ -614,11 +714,35 @@ constexpr int kSolveThreads = 256;
 // pass 2: the refinement, (K + lam I) delta = g + lam (s_old - s0) (ridge:
 // g - lam s0) with the same lam and g the entries' residual vector (ir_part,
 // per work item); the slice becomes s0 + delta.
+template <typename T>
+struct SolveArgs {
+  cx<T>* slices;
+  const T* partials;
+  const int32_t* tile_items;
+  double reg_rel;
+  double reg_floor;
+  int prox;
+  int32_t* flags;
+  int pass;
+  double* ir_lam;
+  cx<T>* ir_old;
+  const float* ir_part;
+};
+
 template <typename T, int R>
-__global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2))) void inner_solve_kernel(
-    cx<T>* slices, const T* partials, const int32_t* tile_items, double reg_rel,
-    double reg_floor, int prox, int32_t* flags, int pass, double* ir_lam, cx<T>* ir_old,
-    const float* ir_part) {
+__device__ __attribute__((always_inline)) inline void inner_solve_body(const SolveArgs<T>& A, int blk) {
+  cx<T>* slices = A.slices;
+  const T* partials = A.partials;
+  const int32_t* tile_items = A.tile_items;
+  double reg_rel = A.reg_rel;
+  double reg_floor = A.reg_floor;
+  int prox = A.prox;
+  int32_t* flags = A.flags;
+  int pass = A.pass;
+  double* ir_lam = A.ir_lam;
+  cx<T>* ir_old = A.ir_old;
+  const float* ir_part = A.ir_part;
+
   typedef SolveGeom<R> G;
   constexpr int D = G::D, WP = G::WP, LD = G::LD, NT = kSolveThreads;
   __shared__ double2 K[D * LD];
@@ -630,7 +754,7 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
   const int tid = threadIdx.x, lane = tid & 63;
   // same XCD-contiguous mapping as the Gram items, so the slice's partial
   // products are read from the L2 that holds them
-  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tile = blk;
   const int it0 = tile_items[tile], it1 = tile_items[tile + 1];
   if (it0 == it1) return;  // no observed entry in this slice: keep it
   {
@@ -768,6 +892,20 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
   if (lane < D) slice[lane] = {T(y.x), T(y.y)};
 }
 
+template <typename T, int R>
+__global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2))) void inner_solve_kernel(SolveArgs<T> A) {
+  inner_solve_body<T, R>(A, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2))) void inner_solve_kernel_batched(const SolveArgs<T>* tasks, const int32_t* block_off,
+    int ntasks) {
+  const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int t = find_task(block_off, ntasks, b);
+  inner_solve_body<T, R>(tasks[t], b - block_off[t]);
+}
+
+
 // ---------------------------------------------------------------------------
 // environment-trie levels
 // ---------------------------------------------------------------------------
@@ -775,54 +913,83 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
 // Right level p (0 <= p < L): node (u, j) = Z^(p+2)[k] * parent, where
 // k = ((ib >> p) << (p+1)) | (jb >> (L-p-1)) with ib >> p = u, and the parent
 // is node (u >> 1, j) of level p+1 (a row of Z^(L+2) when p = L-1).
-template <typename T, int R>
-__global__ __launch_bounds__(256) void env_right_level_kernel(
-    const cx<T>* cores, int64_t n, int L, int c, int p, const int32_t* node_u,
-    const int32_t* node_j, const int32_t* parent, const cx<T>* parent_vec, int count,
-    cx<T>* out) {
-  const int k = xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const uint32_t u = (uint32_t)node_u[k], j = (uint32_t)node_j[k];
-  const uint32_t key = (u << (p + 1)) | ((j / (uint32_t)c) >> (L - p - 1));
-  const cx<T>* Z = cores + inner_off(n, L, R, p + 1) + (int64_t)key * R * R;
-  cx<T> w[R];
-  load_env<T, R>(parent_vec, parent[k], w);
-  mat_vec<T, R>(Z, w);
-  cx<T>* o = out + (int64_t)k * R;
-#pragma unroll
-  for (int a = 0; a < R; ++a) o[a] = w[a];
-}
-
 // Left level p (2 <= p <= L+1): node (w, i) = parent * Z^p[k], where
 // k = ((ib >> (p-2)) << (p-1)) | (jb >> (L-p+1)) with jb >> (L-p+1) = w, and
 // the parent is node (w >> 1, i) of level p-1 (a row of Z^1 when p = 2).
-template <typename T, int R>
-__global__ __launch_bounds__(256) void env_left_level_kernel(
-    const cx<T>* cores, int64_t n, int L, int c, int p, const int32_t* node_w,
-    const int32_t* node_i, const int32_t* parent, const cx<T>* parent_vec, int count,
-    cx<T>* out) {
-  const int k = xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const uint32_t w = (uint32_t)node_w[k], i = (uint32_t)node_i[k];
-  const uint32_t key = (((i / (uint32_t)c) >> (p - 2)) << (p - 1)) | w;
-  const cx<T>* Z = cores + inner_off(n, L, R, p - 1) + (int64_t)key * R * R;
+template <typename T>
+struct EnvArgs {
+  const cx<T>* cores;
+  int64_t n;
+  int L, c, p, count;
+  const int32_t* node_a;  // u (right) or w (left)
+  const int32_t* node_b;  // column j (right) or row i (left)
+  const int32_t* parent;
+  const cx<T>* parent_vec;
+  cx<T>* out;
+};
+
+template <typename T, int R, int RIGHT>
+__device__ __attribute__((always_inline)) inline void env_level_body(const EnvArgs<T>& a,
+                                                                     int blk) {
+  const int k = blk * 256 + (int)threadIdx.x;
+  if (k >= a.count) return;
+  const uint32_t na = (uint32_t)a.node_a[k], nb = (uint32_t)a.node_b[k];
+  const int L = a.L, p = a.p;
   cx<T> v[R];
-  load_env<T, R>(parent_vec, parent[k], v);
-  vec_mat<T, R>(v, Z);
-  cx<T>* o = out + (int64_t)k * R;
+  load_env<T, R>(a.parent_vec, a.parent[k], v);
+  if (RIGHT) {
+    const uint32_t key = (na << (p + 1)) | ((nb / (uint32_t)a.c) >> (L - p - 1));
+    mat_vec<T, R>(a.cores + inner_off(a.n, L, R, p + 1) + (int64_t)key * R * R, v);
+  } else {
+    const uint32_t key = (((nb / (uint32_t)a.c) >> (p - 2)) << (p - 1)) | na;
+    vec_mat<T, R>(v, a.cores + inner_off(a.n, L, R, p - 1) + (int64_t)key * R * R);
+  }
+  cx<T>* o = a.out + (int64_t)k * R;
 #pragma unroll
-  for (int a = 0; a < R; ++a) o[a] = v[a];
+  for (int q = 0; q < R; ++q) o[q] = v[q];
+}
+
+template <typename T, int R, int RIGHT>
+__global__ __launch_bounds__(256) void env_level_kernel(EnvArgs<T> a) {
+  env_level_body<T, R, RIGHT>(a, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R, int RIGHT>
+__global__ __launch_bounds__(256) void env_level_batched(const EnvArgs<T>* tasks,
+                                                         const int32_t* block_off, int ntasks) {
+  const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int t = find_task(block_off, ntasks, b);
+  env_level_body<T, R, RIGHT>(tasks[t], b - block_off[t]);
 }
 
 // Residual on the observed set from the cached left environments of the last
 // core: x = l_(L+1) . Z^(L+2)[j].  Entries in the last core's order.
+template <typename T>
+struct ResObsArgs {
+  const cx<T>* lenv;
+  const int32_t* lidx;
+  const cx<T>* zlast;
+  const int32_t* cols;
+  const cx<T>* vals;
+  int64_t m;
+  int64_t per_block;
+  double* partial;
+};
+
 template <typename T, int R>
-__global__ __launch_bounds__(kResThreads) void residual_observed_kernel(
-    const cx<T>* lenv, const int32_t* lidx, const cx<T>* zlast, const int32_t* cols,
-    const cx<T>* vals, int64_t m, int64_t per_block, double* partial) {
+__device__ __attribute__((always_inline)) inline void residual_observed_body(const ResObsArgs<T>& A, int blk) {
+  const cx<T>* lenv = A.lenv;
+  const int32_t* lidx = A.lidx;
+  const cx<T>* zlast = A.zlast;
+  const int32_t* cols = A.cols;
+  const cx<T>* vals = A.vals;
+  int64_t m = A.m;
+  int64_t per_block = A.per_block;
+  double* partial = A.partial;
+
   __shared__ double s0[kResThreads], s1[kResThreads];
   double a0 = 0.0, a1 = 0.0;
-  const int64_t beg = (int64_t)blockIdx.x * per_block;
+  const int64_t beg = (int64_t)blk * per_block;
   const int64_t end = beg + per_block < m ? beg + per_block : m;
   for (int64_t e = beg + threadIdx.x; e < end; e += kResThreads) {
     cx<T> v[R], z[R];
@@ -847,10 +1014,24 @@ __global__ __launch_bounds__(kResThreads) void residual_observed_kernel(
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = s0[0];
-    partial[2 * blockIdx.x + 1] = s1[0];
+    partial[2 * blk] = s0[0];
+    partial[2 * blk + 1] = s1[0];
   }
 }
+
+template <typename T, int R>
+__global__ __launch_bounds__(kResThreads) void residual_observed_kernel(ResObsArgs<T> A) {
+  residual_observed_body<T, R>(A, (int)blockIdx.x);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kResThreads) void residual_observed_kernel_batched(const ResObsArgs<T>* tasks, const int32_t* block_off,
+    int ntasks) {
+  const int b = (int)blockIdx.x;
+  const int t = find_task(block_off, ntasks, b);
+  residual_observed_body<T, R>(tasks[t], b - block_off[t]);
+}
+
 
 // ---------------------------------------------------------------------------
 // cores: conversion and counter-based random start
@@ -894,6 +1075,30 @@ __global__ void random_cores_kernel(cx<T>* dst, int64_t m, uint64_t seed, double
 // dispatch
 // ---------------------------------------------------------------------------
 // Right level p depends on cores p+1..L+1, left level p on cores 0..p-1.
+// Arguments of the launch computing right (right = 1) or left level q.
+template <typename T, int R>
+EnvArgs<T> env_args(const Problem* P, int q, int right) {
+  const int L = P->L;
+  const cx<T>* cores = (const cx<T>*)P->cores;
+  const EnvLevel& E = right ? P->rlev[q] : P->llev[q];
+  EnvArgs<T> a;
+  a.cores = cores;
+  a.n = P->n;
+  a.L = L;
+  a.c = P->c;
+  a.p = q;
+  a.count = E.count;
+  a.node_a = E.node_a;
+  a.node_b = E.node_b;
+  a.parent = E.parent;
+  if (right)
+    a.parent_vec = (q == L - 1) ? cores + last_off(P->n, L, R) : (const cx<T>*)P->rlev[q + 1].vec;
+  else
+    a.parent_vec = (q == 2) ? cores : (const cx<T>*)P->llev[q - 1].vec;
+  a.out = (cx<T>*)E.vec;
+  return a;
+}
+
 template <typename T, int R>
 bfc_status ensure_right(Problem* P, int p, hipStream_t st) {
   const int L = P->L;
@@ -905,13 +1110,10 @@ bfc_status ensure_right(Problem* P, int p, hipStream_t st) {
       break;
     }
   if (top < 0) return BFC_OK;
-  cx<T>* cores = (cx<T>*)P->cores;
   for (int q = top; q >= p; --q) {
     EnvLevel& E = P->rlev[q];
-    const cx<T>* pv = (q == L - 1) ? cores + last_off(P->n, L, R) : (const cx<T>*)P->rlev[q + 1].vec;
     if (E.count > 0)
-      env_right_level_kernel<T, R><<<grid_for(E.count), 256, 0, st>>>(
-          cores, P->n, L, P->c, q, E.node_a, E.node_b, E.parent, pv, E.count, (cx<T>*)E.vec);
+      env_level_kernel<T, R, 1><<<grid_for(E.count), 256, 0, st>>>(env_args<T, R>(P, q, 1));
     BFC_HIP_TRY(hipGetLastError());
     E.valid = true;
   }
@@ -929,13 +1131,10 @@ bfc_status ensure_left(Problem* P, int p, hipStream_t st) {
       break;
     }
   if (low < 0) return BFC_OK;
-  cx<T>* cores = (cx<T>*)P->cores;
   for (int q = low; q <= p; ++q) {
     EnvLevel& E = P->llev[q];
-    const cx<T>* pv = (q == 2) ? cores : (const cx<T>*)P->llev[q - 1].vec;
     if (E.count > 0)
-      env_left_level_kernel<T, R><<<grid_for(E.count), 256, 0, st>>>(
-          cores, P->n, L, P->c, q, E.node_a, E.node_b, E.parent, pv, E.count, (cx<T>*)E.vec);
+      env_level_kernel<T, R, 0><<<grid_for(E.count), 256, 0, st>>>(env_args<T, R>(P, q, 0));
     BFC_HIP_TRY(hipGetLastError());
     E.valid = true;
   }
@@ -973,9 +1172,9 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
     {
       ProfScope ps(&P->prof, KIND_OUTER, st);
       const unsigned grid = (unsigned)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
-      outer_update_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(
+      outer_update_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(OuterArgs<T>{
           fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks, reg, floor_, prox,
-          P->flags);
+          P->flags});
     }
     BFC_HIP_TRY(hipGetLastError());
   } else {
@@ -996,20 +1195,20 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
       }
       if (!bf16) {
         if (C.group_by_row)
-          inner_gram_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(
-              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
+          inner_gram_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(GramArgs<T>{
+              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials});
         else
-          inner_gram_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(
-              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials);
+          inner_gram_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(GramArgs<T>{
+              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials});
       }
       BFC_HIP_TRY(hipGetLastError());
     }
     cx<T>* slices = cores + inner_off(P->n, L, R, p);
     {
       ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
-      inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(
+      inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(SolveArgs<T>{
           slices, (const T*)P->partials, C.tile_items, reg, floor_, prox, P->flags, bf16 ? 1 : 0,
-          P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part);
+          P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part});
     }
     BFC_HIP_TRY(hipGetLastError());
     if constexpr (std::is_same<T, float>::value) {
@@ -1028,9 +1227,9 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
         BFC_HIP_TRY(hipGetLastError());
         {
           ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
-          inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(
+          inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(SolveArgs<T>{
               slices, (const T*)P->partials, C.tile_items, reg, floor_, prox, P->flags, 2,
-              P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part);
+              P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part});
         }
         BFC_HIP_TRY(hipGetLastError());
       }
@@ -1043,6 +1242,16 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   return BFC_OK;
 }
 
+// Entries per block and block count of a residual over m entries (the block
+// partials fit the problem's reduction scratch).
+inline void residual_split(const Problem* P, int64_t m, int64_t& per, int64_t& nblk) {
+  const int64_t nblk_max = (int64_t)(P->red_len / 2);
+  per = (m + nblk_max - 1) / nblk_max;
+  per = ((per + kResThreads - 1) / kResThreads) * kResThreads;
+  if (per < kResThreads) per = kResThreads;
+  nblk = (m + per - 1) / per;
+}
+
 template <typename T, int R>
 bfc_status residual_observed_t(Problem* P, double* out2, hipStream_t st) {
   const int L = P->L;
@@ -1052,14 +1261,11 @@ bfc_status residual_observed_t(Problem* P, double* out2, hipStream_t st) {
   const cx<T>* lenv = (L + 1 == 1) ? cores : (const cx<T>*)P->llev[L + 1].vec;
   const int32_t* lidx = (L + 1 == 1) ? C.rows : C.lnode;
   const int64_t m = P->nnz;
-  const int64_t nblk_max = (int64_t)(P->red_len / 2);
-  int64_t per = (m + nblk_max - 1) / nblk_max;
-  per = ((per + kResThreads - 1) / kResThreads) * kResThreads;
-  if (per < kResThreads) per = kResThreads;
-  const int64_t nblk = (m + per - 1) / per;
+  int64_t per, nblk;
+  residual_split(P, m, per, nblk);
   ProfScope ps(&P->prof, KIND_RESIDUAL, st);
-  residual_observed_kernel<T, R><<<(unsigned)nblk, kResThreads, 0, st>>>(
-      lenv, lidx, cores + last_off(P->n, L, R), C.cols, (const cx<T>*)C.vals, m, per, P->red);
+  residual_observed_kernel<T, R><<<(unsigned)nblk, kResThreads, 0, st>>>(ResObsArgs<T>{
+      lenv, lidx, cores + last_off(P->n, L, R), C.cols, (const cx<T>*)C.vals, m, per, P->red});
   BFC_HIP_TRY(hipGetLastError());
   residual_final_kernel<<<1, kResThreads, 0, st>>>(P->red, (int)nblk, out2);
   BFC_HIP_TRY(hipGetLastError());
@@ -1141,7 +1347,277 @@ struct ResidualF {
   }
 };
 
+// ---------------------------------------------------------------------------
+// batched sweeps of independent problems
+// ---------------------------------------------------------------------------
+// The launch list of one sweep of every problem, in dependency order (a
+// problem's own order is exactly that of a single sweep, so results are
+// bit-identical to sweeping the problems one by one):
+//   right levels from the top (depth t computes level L-1-t of each problem),
+//   core 0 of every problem,
+//   then per step s = 1 .. max L + 1: left level s (problems with
+//   2 <= s <= L+1), the inner Gram and solve of core s (s <= L), the outer
+//   update of core s (s = L+1).
+// Each entry is one launch per rank present at that step.
+
+template <typename T, typename A>
+bfc_status upload_tasks(Batch* B, int kind, int r, const std::vector<A>& args,
+                        const std::vector<int64_t>& blocks) {
+  if (args.empty()) return BFC_OK;
+  BatchLaunch bl;
+  bl.kind = kind;
+  bl.r = r;
+  bl.ntasks = (int)args.size();
+  std::vector<int32_t> off(args.size() + 1, 0);
+  for (size_t k = 0; k < args.size(); ++k) {
+    const int64_t next = off[k] + blocks[k];
+    if (next > 0x7FFFFFFF) {
+      set_error("batched launch too large");
+      return BFC_EINVAL;
+    }
+    off[k + 1] = (int32_t)next;
+  }
+  bl.blocks = off.back();
+  if (bl.blocks == 0) return BFC_OK;
+  BFC_HIP_TRY(hipMalloc(&bl.tasks, sizeof(A) * args.size()));
+  B->allocs.push_back(bl.tasks);
+  BFC_HIP_TRY(hipMalloc((void**)&bl.block_off, sizeof(int32_t) * off.size()));
+  B->allocs.push_back(bl.block_off);
+  BFC_HIP_TRY(hipMemcpy(bl.tasks, args.data(), sizeof(A) * args.size(), hipMemcpyHostToDevice));
+  BFC_HIP_TRY(hipMemcpy(bl.block_off, off.data(), sizeof(int32_t) * off.size(),
+                        hipMemcpyHostToDevice));
+  (kind == BK_RES || kind == BK_RES_FINAL ? B->resid : B->sweep).push_back(bl);
+  return BFC_OK;
+}
+
+inline double reg_floor_of(const Problem* P) { return P->prec == BFC_C128 ? 0.0 : 0x1p-24; }
+
+template <typename T, int R>
+struct BatchStep {
+  // arguments of every kernel of problem P at step s of the sweep
+  static void env(const Problem* P, int q, int right, std::vector<EnvArgs<T>>& a,
+                  std::vector<int64_t>& b) {
+    const EnvLevel& E = right ? P->rlev[q] : P->llev[q];
+    if (E.count <= 0) return;
+    a.push_back(env_args<T, R>(P, q, right));
+    b.push_back(grid_for(E.count));
+  }
+  static void outer(const Problem* P, int p, std::vector<OuterArgs<T>>& a,
+                    std::vector<int64_t>& b) {
+    const int L = P->L;
+    const CoreLayout& C = P->lay[p];
+    cx<T>* cores = (cx<T>*)P->cores;
+    cx<T>* fibers = cores + (p == 0 ? 0 : last_off(P->n, L, R));
+    const cx<T>* env;
+    const int32_t* idx;
+    if (p == 0) {
+      env = (L == 0) ? cores + last_off(P->n, L, R) : (const cx<T>*)P->rlev[0].vec;
+      idx = (L == 0) ? C.cols : C.rnode;
+    } else {
+      env = (p == 1) ? cores : (const cx<T>*)P->llev[p].vec;
+      idx = (p == 1) ? C.rows : C.lnode;
+    }
+    a.push_back(OuterArgs<T>{fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks,
+                             P->cfg.reg_rel, reg_floor_of(P),
+                             P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0, P->flags});
+    b.push_back(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
+  }
+  static void inner(const Problem* P, int p, std::vector<GramArgs<T>>& grow,
+                    std::vector<int64_t>& brow, std::vector<GramArgs<T>>& gcol,
+                    std::vector<int64_t>& bcol, std::vector<SolveArgs<T>>& sv,
+                    std::vector<int64_t>& bs) {
+    const int L = P->L;
+    const CoreLayout& C = P->lay[p];
+    cx<T>* cores = (cx<T>*)P->cores;
+    const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R) : (const cx<T>*)P->rlev[p].vec;
+    const int32_t* ridx = (p == L) ? C.cols : C.rnode;
+    const cx<T>* lenv = (p == 1) ? cores : (const cx<T>*)P->llev[p].vec;
+    const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
+    if (C.nitems > 0) {
+      GramArgs<T> g{lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items,
+                    (T*)P->partials};
+      if (C.group_by_row) {
+        grow.push_back(g);
+        brow.push_back(C.nitems);
+      } else {
+        gcol.push_back(g);
+        bcol.push_back(C.nitems);
+      }
+    }
+    sv.push_back(SolveArgs<T>{cores + inner_off(P->n, L, R, p), (const T*)P->partials,
+                              C.tile_items, P->cfg.reg_rel, reg_floor_of(P),
+                              P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0, P->flags, 0,
+                              nullptr, nullptr, nullptr});
+    bs.push_back(C.nblocks);
+  }
+  static void resid(Problem* P, double* out, std::vector<ResObsArgs<T>>& a,
+                    std::vector<int64_t>& b, std::vector<ResFinalArgs>& f) {
+    const int L = P->L;
+    const CoreLayout& C = P->lay[L + 1];
+    cx<T>* cores = (cx<T>*)P->cores;
+    const cx<T>* lenv = (L + 1 == 1) ? cores : (const cx<T>*)P->llev[L + 1].vec;
+    const int32_t* lidx = (L + 1 == 1) ? C.rows : C.lnode;
+    int64_t per, nblk;
+    residual_split(P, P->nnz, per, nblk);
+    a.push_back(ResObsArgs<T>{lenv, lidx, cores + last_off(P->n, L, R), C.cols,
+                              (const cx<T>*)C.vals, P->nnz, per, P->red});
+    b.push_back(nblk);
+    f.push_back(ResFinalArgs{P->red, (int)nblk, out});
+  }
+};
+
+// All problems of one rank R: append their launches for one phase.
+template <typename T, int R>
+struct BatchPlanR {
+  static bfc_status run(Batch* B, const std::vector<Problem*>& ps, int phase, int step) {
+    typedef BatchStep<T, R> S;
+    if (phase == 0) {  // right level at depth `step` from the top
+      std::vector<EnvArgs<T>> a;
+      std::vector<int64_t> b;
+      for (Problem* P : ps)
+        if (step < P->L) S::env(P, P->L - 1 - step, 1, a, b);
+      return upload_tasks<T>(B, BK_ENV_RIGHT, R, a, b);
+    }
+    if (phase == 1) {  // left level `step`
+      std::vector<EnvArgs<T>> a;
+      std::vector<int64_t> b;
+      for (Problem* P : ps)
+        if (step >= 2 && step <= P->L + 1) S::env(P, step, 0, a, b);
+      return upload_tasks<T>(B, BK_ENV_LEFT, R, a, b);
+    }
+    if (phase == 2) {  // inner core `step`
+      std::vector<GramArgs<T>> gr, gc;
+      std::vector<SolveArgs<T>> sv;
+      std::vector<int64_t> br, bc, bs;
+      for (Problem* P : ps)
+        if (step >= 1 && step <= P->L) S::inner(P, step, gr, br, gc, bc, sv, bs);
+      BFC_TRY(upload_tasks<T>(B, BK_GRAM_ROW, R, gr, br));
+      BFC_TRY(upload_tasks<T>(B, BK_GRAM_COL, R, gc, bc));
+      return upload_tasks<T>(B, BK_SOLVE, R, sv, bs);
+    }
+    if (phase == 3) {  // outer core 0 (step 0) or L+1 (step = L+1)
+      std::vector<OuterArgs<T>> a;
+      std::vector<int64_t> b;
+      for (Problem* P : ps)
+        if (step == 0 || step == P->L + 1) S::outer(P, step, a, b);
+      return upload_tasks<T>(B, BK_OUTER, R, a, b);
+    }
+    // phase 4: residual norms
+    std::vector<ResObsArgs<T>> a;
+    std::vector<int64_t> b;
+    std::vector<ResFinalArgs> f;
+    std::vector<int64_t> one;
+    for (Problem* P : ps) {
+      size_t k = 0;
+      while (B->probs[k] != P) ++k;
+      S::resid(P, B->res + 2 * k, a, b, f);
+      one.push_back(1);
+    }
+    BFC_TRY(upload_tasks<T>(B, BK_RES, R, a, b));
+    return upload_tasks<T>(B, BK_RES_FINAL, R, f, one);
+  }
+};
+
+template <typename T>
+bfc_status batch_plan_phase(Batch* B, int phase, int step) {
+  for (int r = 1; r <= BFC_MAX_RANK; ++r) {
+    std::vector<Problem*> ps;
+    for (Problem* P : B->probs)
+      if (P->r == r) ps.push_back(P);
+    if (ps.empty()) continue;
+    bfc_status s = BFC_OK;
+    switch (r) {
+#define BFC_PLAN(RR) \
+  case RR:           \
+    s = BatchPlanR<T, RR>::run(B, ps, phase, step); \
+    break;
+      BFC_PLAN(1) BFC_PLAN(2) BFC_PLAN(3) BFC_PLAN(4) BFC_PLAN(5) BFC_PLAN(6) BFC_PLAN(7)
+      BFC_PLAN(8)
+#undef BFC_PLAN
+    }
+    BFC_TRY(s);
+  }
+  return BFC_OK;
+}
+
+template <typename T>
+bfc_status build_batch_plan_t(Batch* B) {
+  int maxL = 0;
+  for (Problem* P : B->probs) maxL = P->L > maxL ? P->L : maxL;
+  for (int t = 0; t < maxL; ++t) BFC_TRY(batch_plan_phase<T>(B, 0, t));
+  BFC_TRY(batch_plan_phase<T>(B, 3, 0));
+  for (int s = 1; s <= maxL + 1; ++s) {
+    BFC_TRY(batch_plan_phase<T>(B, 1, s));
+    BFC_TRY(batch_plan_phase<T>(B, 2, s));
+    BFC_TRY(batch_plan_phase<T>(B, 3, s));
+  }
+  return batch_plan_phase<T>(B, 4, 0);
+}
+
+template <typename T, int R>
+bfc_status launch_batched_r(const BatchLaunch& bl, hipStream_t st) {
+  const unsigned g = (unsigned)bl.blocks;
+  switch (bl.kind) {
+    case BK_ENV_RIGHT:
+      env_level_batched<T, R, 1><<<g, 256, 0, st>>>((const EnvArgs<T>*)bl.tasks, bl.block_off,
+                                                     bl.ntasks);
+      break;
+    case BK_ENV_LEFT:
+      env_level_batched<T, R, 0><<<g, 256, 0, st>>>((const EnvArgs<T>*)bl.tasks, bl.block_off,
+                                                     bl.ntasks);
+      break;
+    case BK_OUTER:
+      outer_update_kernel_batched<T, R><<<g, kOuterThreads, 0, st>>>(
+          (const OuterArgs<T>*)bl.tasks, bl.block_off, bl.ntasks);
+      break;
+    case BK_GRAM_ROW:
+      inner_gram_kernel_batched<T, R, 1><<<g, 64, 0, st>>>((const GramArgs<T>*)bl.tasks,
+                                                           bl.block_off, bl.ntasks);
+      break;
+    case BK_GRAM_COL:
+      inner_gram_kernel_batched<T, R, 0><<<g, 64, 0, st>>>((const GramArgs<T>*)bl.tasks,
+                                                           bl.block_off, bl.ntasks);
+      break;
+    case BK_SOLVE:
+      inner_solve_kernel_batched<T, R><<<g, kSolveThreads, 0, st>>>(
+          (const SolveArgs<T>*)bl.tasks, bl.block_off, bl.ntasks);
+      break;
+    case BK_RES:
+      residual_observed_kernel_batched<T, R><<<g, kResThreads, 0, st>>>(
+          (const ResObsArgs<T>*)bl.tasks, bl.block_off, bl.ntasks);
+      break;
+    case BK_RES_FINAL:
+      residual_final_batched<<<bl.ntasks, kResThreads, 0, st>>>((const ResFinalArgs*)bl.tasks);
+      break;
+  }
+  BFC_HIP_TRY(hipGetLastError());
+  return BFC_OK;
+}
+
+template <typename T>
+bfc_status launch_batched(const BatchLaunch& bl, hipStream_t st) {
+  switch (bl.r) {
+#define BFC_LB(RR) \
+  case RR:         \
+    return launch_batched_r<T, RR>(bl, st);
+    BFC_LB(1) BFC_LB(2) BFC_LB(3) BFC_LB(4) BFC_LB(5) BFC_LB(6) BFC_LB(7) BFC_LB(8)
+#undef BFC_LB
+  }
+  set_error("rank out of range");
+  return BFC_EINVAL;
+}
+
 }  // namespace
+
+bfc_status build_batch_plan(Batch* B) {
+  return B->prec == BFC_C128 ? build_batch_plan_t<double>(B) : build_batch_plan_t<float>(B);
+}
+
+bfc_status launch_batch(const std::vector<BatchLaunch>& plan, int prec, hipStream_t st) {
+  for (const BatchLaunch& bl : plan)
+    BFC_TRY(prec == BFC_C128 ? launch_batched<double>(bl, st) : launch_batched<float>(bl, st));
+  return BFC_OK;
+}
 
 size_t inner_partial_bytes(int prec, int r) {
   const int W = r * r + 2 * r;

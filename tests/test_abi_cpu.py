@@ -81,3 +81,17 @@ def test_null_problem_calls():
     out = (ctypes.c_double * 2)()
     assert lib.bfc_residual(None, 0, None, None, None, out, None) == _lib.BFC_EINVAL
     lib.bfc_destroy(None)
+
+
+def test_batch_argument_checks():
+    lib = _lib.load()
+    h = ctypes.c_void_p(1)
+    assert lib.bfc_batch_create(None, 0, ctypes.byref(h)) == _lib.BFC_EINVAL
+    assert h.value is None  # cleared on error
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.bfc_batch_create(arr, 2, ctypes.byref(h)) == _lib.BFC_EINVAL
+    assert lib.bfc_batch_create(arr, 2, None) == _lib.BFC_EINVAL
+    assert lib.bfc_batch_sweep(None, None) == _lib.BFC_EINVAL
+    out = (ctypes.c_double * 2)()
+    assert lib.bfc_batch_residuals(None, out, None) == _lib.BFC_EINVAL
+    assert lib.bfc_batch_destroy(None) == _lib.BFC_OK

@@ -5,6 +5,7 @@ produces operator entries, observed index sets and random starting cores.
 """
 from .generators import (  # noqa: F401
     WORKLOADS,
+    batched_instances,
     Workload,
     green_line_entries,
     green_planes_entries,
