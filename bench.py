@@ -316,6 +316,55 @@ def stats_summary(stats_dir, bench_json, out, command):
     print("\n".join(lines))
 
 
+def batched_record(bfc, torch, dev, steps):
+    """The 64-instance batching workload (n = 1024..16384, L = 4..8, r = 4/6,
+    6 n log2 n entries each): whole-batch throughput of batched sweeps (one
+    launch per kernel kind and step, captured graph) against the same sweeps
+    issued problem by problem (each a captured graph), on one stream."""
+    from workloads import batched_instances, make_workload
+
+    ws = [make_workload(**s) for s in batched_instances(64)]
+    total = sum(w.nnz for w in ws)
+
+    def mk(w):
+        cfg = bfc.Config(n=w.n, L=w.L, r=w.r, precision="c64", reg_rel=1e-10)
+        return bfc.init_cores(cfg, torch.as_tensor(w.rows, device=dev),
+                              torch.as_tensor(w.cols, device=dev),
+                              torch.as_tensor(w.vals, device=dev),
+                              torch.as_tensor(bfc.flatten_cores(w.cores0), device=dev), device=dev)
+
+    probs = [mk(w) for w in ws]
+    b = bfc.batch_create(probs)
+
+    def timed(fn, k):
+        fn()  # warm-up (captures the graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    t_batch = timed(lambda: bfc.batch_sweep(b), steps)
+    t_each = timed(lambda: [bfc.sweep(p) for p in probs], steps)
+    res = bfc.batch_residuals(b)
+    worst = max((num / den) ** 0.5 for num, den in res)
+    b.close()
+    for p in probs:
+        p.close()
+    return {
+        "workload": "64 instances, n in {1024..16384} (16/16/16/8/8), L = log2(n/64), "
+                    "r = 4/6, omega = pi sqrt(n), 6 n log2 n entries each",
+        "instances": len(ws), "entries": total, "precision": "c64",
+        "batched": {"value": round(total / t_batch, 1), "unit": "entries/s",
+                    "ms_per_sweep": round(1e3 * t_batch, 4)},
+        "one_by_one": {"value": round(total / t_each, 1), "unit": "entries/s",
+                       "ms_per_sweep": round(1e3 * t_each, 4)},
+        "speedup": round(t_each / t_batch, 3),
+        "worst_train_rel_err_after": worst,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +376,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -531,6 +581,8 @@ def main():
             "bf16gram": out.get("bf16gram", {}).get("final_test_err"),
         }
 
+    if not args.no_batch:
+        out["batching"] = batched_record(bfc, torch, dev, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     prob.close()
