@@ -252,10 +252,37 @@ const char* bfc_last_error(void);
  * bfc_batch_destroy: releases the plan (not the problems); NULL is ignored.
  */
 typedef struct bfc_batch bfc_batch;
+/* (bfc_batch_create etc. below.)  A batch re-plans itself when a problem's
+ * work items change (bfc_set_item_size / bfc_autotune_item_size). */
 bfc_status bfc_batch_create(bfc_problem* const* problems, int32_t count, bfc_batch** out);
 bfc_status bfc_batch_sweep(bfc_batch* b, void* hip_stream);
 bfc_status bfc_batch_residuals(bfc_batch* b, double* out_sq, void* hip_stream);
 bfc_status bfc_batch_destroy(bfc_batch* b);
+
+/*
+ * Tile shape of the inner-core Gram (the subgroup work items of a1, each one
+ * wavefront): subgroups per work item, 0 for the automatic rule (at least 128,
+ * and enough that a core has about 16384 items), else a multiple of 64 in
+ * [64, 65536].  Larger items mean fewer partial products for the slice solve
+ * to sum, smaller ones more wavefronts in flight.  Rebuilds every inner core's
+ * items (synchronizes hip_stream), grows the partial-product buffers when
+ * needed and drops the captured sweep graph.  Results change only by the
+ * order of the FP partial sums.
+ */
+bfc_status bfc_set_item_size(bfc_problem* p, int32_t subgroups, void* hip_stream);
+
+/*
+ * Autotuner for the tile shape above: for each candidate (NULL: 64, 128, 256,
+ * 512) sets it on every problem, runs one warm-up sweep and `sweeps` timed
+ * sweeps (batched when count > 1, HIP events on hip_stream), and keeps the
+ * fastest.  Every problem's cores are restored bit-exactly after each trial
+ * and at the end (its solve-failure counters are cleared); *chosen receives
+ * the selected size, ms_per_sweep[c] (optional, ncand entries) the measured
+ * time of candidate c.  Synchronous.
+ */
+bfc_status bfc_autotune_item_size(bfc_problem* const* problems, int32_t count, int32_t sweeps,
+                                  const int32_t* candidates, int32_t ncand, int32_t* chosen,
+                                  double* ms_per_sweep, void* hip_stream);
 
 #ifdef __cplusplus
 }

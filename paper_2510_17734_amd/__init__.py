@@ -34,4 +34,6 @@ from .api import (  # noqa: F401
     sync_status,
     unflatten_cores,
     use_graphs,
+    set_item_size,
+    autotune_item_size,
 )

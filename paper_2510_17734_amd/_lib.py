@@ -52,6 +52,8 @@ EXPORTS = (
     "bfc_batch_sweep",
     "bfc_batch_residuals",
     "bfc_batch_destroy",
+    "bfc_set_item_size",
+    "bfc_autotune_item_size",
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
@@ -127,6 +129,12 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_batch_residuals.restype = i32
     lib.bfc_batch_destroy.argtypes = [P]
     lib.bfc_batch_destroy.restype = i32
+    lib.bfc_set_item_size.argtypes = [P, i32, vp]
+    lib.bfc_set_item_size.restype = i32
+    lib.bfc_autotune_item_size.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(i32), i32,
+                                           ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                           vp]
+    lib.bfc_autotune_item_size.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

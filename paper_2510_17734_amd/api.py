@@ -307,3 +307,22 @@ def batch_residuals(b: Batch, stream=None):
     out = (ctypes.c_double * (2 * k))()
     _check(_lib.load().bfc_batch_residuals(b.handle, out, _stream(stream)), "bfc_batch_residuals")
     return [(float(out[2 * q]), float(out[2 * q + 1])) for q in range(k)]
+
+
+def set_item_size(p: Problem, subgroups: int, stream=None):
+    """bfc_set_item_size: subgroups per inner-Gram work item (0 = automatic)."""
+    _check(_lib.load().bfc_set_item_size(p.handle, int(subgroups), _stream(stream)),
+           "bfc_set_item_size")
+
+
+def autotune_item_size(problems, sweeps: int = 2, candidates=(64, 128, 256, 512), stream=None):
+    """bfc_autotune_item_size: returns (chosen size, {candidate: ms per sweep})."""
+    problems = list(problems)
+    arr = (ctypes.c_void_p * len(problems))(*[p.handle for p in problems])
+    cand = (ctypes.c_int32 * len(candidates))(*candidates)
+    ms = (ctypes.c_double * len(candidates))()
+    chosen = ctypes.c_int32()
+    _check(_lib.load().bfc_autotune_item_size(arr, len(problems), int(sweeps), cand,
+                                              len(candidates), ctypes.byref(chosen), ms,
+                                              _stream(stream)), "bfc_autotune_item_size")
+    return int(chosen.value), {c: float(ms[k]) for k, c in enumerate(candidates)}

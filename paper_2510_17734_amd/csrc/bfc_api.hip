@@ -25,6 +25,17 @@ bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes) {
   return BFC_OK;
 }
 
+bfc_status dev_free(Problem* P, void* ptr) {
+  for (size_t k = 0; k < P->allocs.size(); ++k)
+    if (P->allocs[k] == ptr) {
+      P->allocs.erase(P->allocs.begin() + k);
+      BFC_HIP_TRY(hipFree(ptr));
+      return BFC_OK;
+    }
+  set_error("internal: freeing an unknown allocation");
+  return BFC_EHIP;
+}
+
 hipEvent_t Profiler::take() {
   if (pool.empty()) {
     hipEvent_t e = nullptr;
@@ -453,13 +464,38 @@ void bfc_destroy(bfc_problem* p) {
 // ---------------------------------------------------------------------------
 struct bfc_batch : public bfc::Batch {};
 
-namespace {
-void free_batch(bfc_batch* B) {
+namespace bfc {
+// Release the launch plan and its graph (the residual buffers stay).
+void free_batch_plan(Batch* B) {
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
-  for (void* p : B->allocs) (void)hipFree(p);
+  B->exec = nullptr;
+  B->graph = nullptr;
+  for (void* p : B->allocs)
+    if (p != B->res) (void)hipFree(p);
+  B->allocs.assign(1, B->res);
+  B->sweep.clear();
+  B->resid.clear();
+}
+}  // namespace bfc
+
+namespace {
+void free_batch(bfc_batch* B) {
+  free_batch_plan(B);
+  if (B->res) (void)hipFree(B->res);
   if (B->res_host) (void)hipHostFree(B->res_host);
   delete B;
+}
+
+// Rebuild the plan when a problem's work items changed since it was made.
+bfc_status refresh_batch(bfc_batch* B) {
+  bool stale = false;
+  for (size_t k = 0; k < B->probs.size(); ++k)
+    stale = stale || B->versions[k] != B->probs[k]->layout_version;
+  if (!stale) return BFC_OK;
+  free_batch_plan(B);
+  for (size_t k = 0; k < B->probs.size(); ++k) B->versions[k] = B->probs[k]->layout_version;
+  return build_batch_plan(B);
 }
 }  // namespace
 
@@ -510,6 +546,7 @@ bfc_status bfc_batch_create(bfc_problem* const* problems, int32_t count, bfc_bat
     return BFC_ENOMEM;
   }
   B->allocs.push_back(B->res);
+  for (bfc::Problem* P : B->probs) B->versions.push_back(P->layout_version);
   if ((s = build_batch_plan(B)) != BFC_OK) {
     free_batch(B);
     return s;
@@ -524,6 +561,7 @@ bfc_status bfc_batch_sweep(bfc_batch* b, void* hip_stream) {
     return BFC_EINVAL;
   }
   hipStream_t st = (hipStream_t)hip_stream;
+  BFC_TRY(refresh_batch(b));
   if (st != nullptr) {
     if (!b->exec) {
       BFC_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -556,6 +594,7 @@ bfc_status bfc_batch_residuals(bfc_batch* b, double* out_sq, void* hip_stream) {
     return BFC_EINVAL;
   }
   hipStream_t st = (hipStream_t)hip_stream;
+  BFC_TRY(refresh_batch(b));
   const size_t k = b->probs.size();
   // the residuals read the last left level of every problem: bring stale ones
   // up to date (a no-op right after a batched sweep)
@@ -590,4 +629,152 @@ bfc_status bfc_batch_residuals(bfc_batch* b, double* out_sq, void* hip_stream) {
 bfc_status bfc_batch_destroy(bfc_batch* b) {
   if (b) free_batch(b);
   return BFC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// work-item size and its autotuner
+// ---------------------------------------------------------------------------
+bfc_status bfc_set_item_size(bfc_problem* p, int32_t subgroups, void* hip_stream) {
+  if (!p || subgroups < 0 || subgroups > 65536 || subgroups % 64 != 0) {
+    set_error("item size must be 0 (automatic) or a multiple of 64 in [64, 65536]");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  p->item_size = subgroups;
+  int32_t max_items = 0;
+  for (int q = 1; q <= p->L; ++q) {
+    BFC_TRY(build_items(p, q, st));
+    max_items = std::max(max_items, p->lay[q].nitems);
+  }
+  if (max_items > p->max_items) {
+    // grow the per-item buffers; their old contents are scratch
+    p->max_items = max_items;
+    if (p->partials) BFC_TRY(dev_free(p, p->partials));
+    p->partials = nullptr;
+    p->partials_bytes = (size_t)max_items * inner_partial_bytes(p->prec, p->r);
+    BFC_TRY(dev_alloc(p, &p->partials, p->partials_bytes));
+    if (p->ir_part) {
+      BFC_TRY(dev_free(p, p->ir_part));
+      p->ir_part = nullptr;
+      BFC_TRY(dev_alloc(p, &p->ir_part, (size_t)max_items * 2 * p->r * p->r * sizeof(float)));
+    }
+  }
+  // the captured sweep holds the old launch shapes and buffers
+  if (p->sweep_exec) (void)hipGraphExecDestroy(p->sweep_exec);
+  if (p->sweep_graph) (void)hipGraphDestroy(p->sweep_graph);
+  p->sweep_exec = nullptr;
+  p->sweep_graph = nullptr;
+  ++p->layout_version;
+  return BFC_OK;
+}
+
+bfc_status bfc_autotune_item_size(bfc_problem* const* problems, int32_t count, int32_t sweeps,
+                                  const int32_t* candidates, int32_t ncand, int32_t* chosen,
+                                  double* ms_per_sweep, void* hip_stream) {
+  static const int32_t kDefault[] = {64, 128, 256, 512};
+  if (!problems || count < 1 || sweeps < 1 || !chosen || (candidates && ncand < 1)) {
+    set_error("bad autotune arguments");
+    return BFC_EINVAL;
+  }
+  if (!candidates) {
+    candidates = kDefault;
+    ncand = 4;
+  }
+  for (int32_t c = 0; c < ncand; ++c)
+    if (candidates[c] < 64 || candidates[c] % 64 != 0 || candidates[c] > 65536) {
+      set_error("autotune candidates must be multiples of 64 in [64, 65536]");
+      return BFC_EINVAL;
+    }
+  hipStream_t st = (hipStream_t)hip_stream;
+  // the trial sweeps change the cores: keep a copy of every problem's cores
+  std::vector<void*> saved(count, nullptr);
+  auto release = [&]() {
+    for (void* q : saved)
+      if (q) (void)hipFree(q);
+  };
+  for (int32_t k = 0; k < count; ++k) {
+    bfc_problem* P = problems[k];
+    if (!P) {
+      release();
+      set_error("null problem");
+      return BFC_EINVAL;
+    }
+    const size_t bytes = (size_t)P->nparams * P->elem;
+    if (hipMalloc(&saved[k], bytes) != hipSuccess) {
+      saved[k] = nullptr;
+      release();
+      set_error("autotune: no memory for the core copies");
+      return BFC_ENOMEM;
+    }
+    if (hipMemcpyAsync(saved[k], P->cores, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      release();
+      set_error("autotune: copy failed");
+      return BFC_EHIP;
+    }
+  }
+  auto restore = [&]() -> bfc_status {
+    for (int32_t k = 0; k < count; ++k) {
+      bfc_problem* P = problems[k];
+      BFC_HIP_TRY(hipMemcpyAsync(P->cores, saved[k], (size_t)P->nparams * P->elem,
+                                 hipMemcpyDeviceToDevice, st));
+      BFC_HIP_TRY(hipMemsetAsync(P->flags, 0, 8, st));
+      invalidate_envs(P);
+    }
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+    return BFC_OK;
+  };
+  bfc_batch* B = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bfc_status s = BFC_OK;
+  double best = 0.0;
+  int32_t best_size = candidates[0];
+  do {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      set_error("autotune: hipEventCreate failed");
+      s = BFC_EHIP;
+      break;
+    }
+    if (count > 1 && (s = bfc_batch_create(problems, count, &B)) != BFC_OK) break;
+    auto one_sweep = [&]() -> bfc_status {
+      if (B) return bfc_batch_sweep(B, st);
+      return bfc_sweep(problems[0], st);
+    };
+    for (int32_t c = 0; c < ncand && s == BFC_OK; ++c) {
+      for (int32_t k = 0; k < count && s == BFC_OK; ++k)
+        s = bfc_set_item_size(problems[k], candidates[c], st);
+      if (s != BFC_OK) break;
+      if ((s = one_sweep()) != BFC_OK) break;  // warm-up (and graph capture)
+      if (hipEventRecord(e0, st) != hipSuccess) s = BFC_EHIP;
+      for (int32_t t = 0; t < sweeps && s == BFC_OK; ++t) s = one_sweep();
+      if (s != BFC_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        set_error("autotune: event timing failed");
+        s = BFC_EHIP;
+        break;
+      }
+      const double per = ms / sweeps;
+      if (ms_per_sweep) ms_per_sweep[c] = per;
+      if (c == 0 || per < best) {
+        best = per;
+        best_size = candidates[c];
+      }
+      if ((s = restore()) != BFC_OK) break;
+    }
+  } while (false);
+  if (B) bfc_batch_destroy(B);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s == BFC_OK) {
+    for (int32_t k = 0; k < count && s == BFC_OK; ++k)
+      s = bfc_set_item_size(problems[k], best_size, st);
+    if (s == BFC_OK) s = restore();
+    if (s == BFC_OK) *chosen = best_size;
+  } else {
+    (void)restore();
+  }
+  release();
+  return s;
 }

@@ -91,6 +91,8 @@ struct CoreLayout {
   int32_t nitems = 0;
   WorkItem* items = nullptr;
   int32_t* tile_items = nullptr;  // nblocks + 1: item range of each slice
+  int32_t items_cap = 0;          // WorkItems the items array holds
+  std::vector<int32_t> tile_sub;  // host: first subgroup of each slice, nblocks + 1
   // environment node of every sorted entry (nullptr where the environment is
   // a row of Z^1 or of Z^(L+2) itself)
   int32_t* lnode = nullptr;
@@ -161,6 +163,8 @@ struct Problem {
   double* red_host = nullptr;        // pinned, 2 doubles
   std::vector<void*> allocs;         // everything hipMalloc'd
   int32_t max_items = 0;
+  int32_t item_size = 0;             // subgroups per work item (0: automatic rule)
+  int64_t layout_version = 0;        // bumped when work items are rebuilt
   // one full sweep captured as a HIP graph (launched by bfc_sweep when
   // graphs are enabled and per-kernel profiling is off)
   bool use_graph = true;
@@ -190,6 +194,7 @@ struct BatchLaunch {
 // kind of every problem that needs it at that step of the sweep.
 struct Batch {
   std::vector<Problem*> probs;
+  std::vector<int64_t> versions;   // layout_version of each problem when planned
   int prec = BFC_C64;
   std::vector<BatchLaunch> sweep;  // one sweep of every problem, in dependency order
   std::vector<BatchLaunch> resid;  // observed-set residual norms of every problem
@@ -200,6 +205,7 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
 };
 bfc_status build_batch_plan(Batch* B);
+void free_batch_plan(Batch* B);
 bfc_status launch_batch(const std::vector<BatchLaunch>& plan, int prec, hipStream_t st);
 
 // geometry helpers (host)
@@ -211,6 +217,8 @@ inline int64_t num_params(int64_t n, int L, int r) {
 bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols,
                         const void* d_vals, hipStream_t st);
 bfc_status launch_sweep_core(Problem* P, int core, hipStream_t st);
+bfc_status build_items(Problem* P, int core, hipStream_t st);
+bfc_status dev_free(Problem* P, void* ptr);
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
                           void* out, hipStream_t st);
 bfc_status launch_residual(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,

@@ -191,6 +191,41 @@ struct Scratch {
 
 }  // namespace
 
+// Work items of inner core p: chunks of P->item_size subgroups (automatic
+// when 0: at least 128 and enough to keep the item count near 16384), never
+// across slices.  Reuses the items array while it is large enough.
+bfc_status build_items(Problem* P, int p, hipStream_t st) {
+  CoreLayout& C = P->lay[p];
+  int64_t ch = P->item_size;
+  if (ch <= 0) {
+    const int64_t per_item_target = (int64_t)C.nsub / 16384 + 1;
+    ch = std::max<int64_t>(128, ((per_item_target + 63) / 64) * 64);
+  }
+  std::vector<WorkItem> items;
+  std::vector<int32_t> tile_items(C.nblocks + 1);
+  const std::vector<int32_t>& hts = C.tile_sub;
+  for (int b = 0; b < C.nblocks; ++b) {
+    tile_items[b] = (int32_t)items.size();
+    for (int64_t s = hts[b]; s < hts[b + 1]; s += ch)
+      items.push_back({b, (int32_t)s, (int32_t)std::min<int64_t>(s + ch, hts[b + 1]), 0});
+  }
+  tile_items[C.nblocks] = (int32_t)items.size();
+  if ((int64_t)items.size() > C.items_cap || !C.items) {
+    if (C.items) BFC_TRY(dev_free(P, C.items));
+    C.items = nullptr;
+    C.items_cap = (int32_t)std::max<size_t>(1, items.size());
+    BFC_TRY(dev_alloc(P, (void**)&C.items, (size_t)C.items_cap * sizeof(WorkItem)));
+  }
+  C.nitems = (int32_t)items.size();
+  if (!items.empty())
+    BFC_HIP_TRY(hipMemcpyAsync(C.items, items.data(), items.size() * sizeof(WorkItem),
+                               hipMemcpyHostToDevice, st));
+  BFC_HIP_TRY(hipMemcpyAsync(C.tile_items, tile_items.data(), (C.nblocks + 1) * 4,
+                             hipMemcpyHostToDevice, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  return BFC_OK;
+}
+
 bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols,
                         const void* d_vals, hipStream_t st) {
   const int64_t nnz = P->nnz;
@@ -362,30 +397,12 @@ bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols
     tile_subs_kernel<<<grid_for(C.nblocks + 1), 256, 0, st>>>(C.blk_off, tmp2, nnz, C.nblocks,
                                                               C.nsub, tile_sub);
     BFC_HIP_TRY(hipGetLastError());
-    std::vector<int32_t> hts(C.nblocks + 1);
-    BFC_HIP_TRY(hipMemcpyAsync(hts.data(), tile_sub, (C.nblocks + 1) * 4, hipMemcpyDeviceToHost,
-                               st));
+    C.tile_sub.assign(C.nblocks + 1, 0);
+    BFC_HIP_TRY(hipMemcpyAsync(C.tile_sub.data(), tile_sub, (C.nblocks + 1) * 4,
+                               hipMemcpyDeviceToHost, st));
     BFC_HIP_TRY(hipStreamSynchronize(st));
-    // work items: chunks of ch subgroups (a multiple of 64), never across slices
-    const int64_t per_item_target = (int64_t)C.nsub / 16384 + 1;
-    const int ch = (int)std::max<int64_t>(128, ((per_item_target + 63) / 64) * 64);
-    std::vector<WorkItem> items;
-    std::vector<int32_t> tile_items(C.nblocks + 1);
-    for (int b = 0; b < C.nblocks; ++b) {
-      tile_items[b] = (int32_t)items.size();
-      for (int32_t s = hts[b]; s < hts[b + 1]; s += ch)
-        items.push_back({b, s, std::min<int32_t>(s + ch, hts[b + 1]), 0});
-    }
-    tile_items[C.nblocks] = (int32_t)items.size();
-    C.nitems = (int32_t)items.size();
-    BFC_TRY(dev_alloc(P, (void**)&C.items, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
     BFC_TRY(dev_alloc(P, (void**)&C.tile_items, (C.nblocks + 1) * 4));
-    if (!items.empty())
-      BFC_HIP_TRY(hipMemcpyAsync(C.items, items.data(), items.size() * sizeof(WorkItem),
-                                 hipMemcpyHostToDevice, st));
-    BFC_HIP_TRY(hipMemcpyAsync(C.tile_items, tile_items.data(), (C.nblocks + 1) * 4,
-                               hipMemcpyHostToDevice, st));
-    BFC_HIP_TRY(hipStreamSynchronize(st));
+    BFC_TRY(build_items(P, p, st));
     max_items = std::max(max_items, C.nitems);
   }
   P->max_items = max_items;

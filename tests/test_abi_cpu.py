@@ -95,3 +95,11 @@ def test_batch_argument_checks():
     out = (ctypes.c_double * 2)()
     assert lib.bfc_batch_residuals(None, out, None) == _lib.BFC_EINVAL
     assert lib.bfc_batch_destroy(None) == _lib.BFC_OK
+
+
+def test_item_size_argument_checks():
+    lib = _lib.load()
+    assert lib.bfc_set_item_size(None, 64, None) == _lib.BFC_EINVAL
+    chosen = ctypes.c_int32()
+    assert lib.bfc_autotune_item_size(None, 1, 1, None, 0, ctypes.byref(chosen), None,
+                                      None) == _lib.BFC_EINVAL

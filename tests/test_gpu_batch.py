@@ -142,3 +142,73 @@ def test_batch_rejects_bad_arguments(mixed):
         bfc.batch_create([])
     for p in (a, c, d):
         p.close()
+
+
+# --------------------------------------------------------------------------
+# work-item size (the inner Gram's tile shape) and its autotuner
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("size", [64, 512, 0])
+def test_item_size_keeps_parity(size):
+    w = make_workload(**batched_instances(64)[1])  # n = 1024, r = 6
+    p = _make(w, "c128")
+    bfc.set_item_size(p, size)
+    stats = bfc.core_stats(p, 2)
+    if size:
+        assert stats["items"] >= -(-stats["subgroups"] // size)
+    ref = w.cores0
+    for q in range(w.L + 2):
+        bfc.sweep_core(p, q)
+        ref = oracle.update_core(ref, q, w.rows, w.cols, w.vals, w.L)
+    got = bfc.unflatten_cores(bfc.get_cores(p).cpu().numpy(), w.n, w.L, w.r)
+    for q in range(w.L + 2):
+        err = np.max(np.abs(got[q] - ref[q])) / np.max(np.abs(ref[q]))
+        assert err <= 1e-9, (size, q, err)
+    p.close()
+
+
+def test_batch_replans_after_item_size_change(mixed):
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        single = [_make(w, "c64") for w in mixed]
+        batched = [_make(w, "c64") for w in mixed]
+        b = bfc.batch_create(batched)
+        bfc.batch_sweep(b)
+        for p in single:
+            bfc.sweep(p)
+        for p in single + batched:
+            bfc.set_item_size(p, 64)
+        bfc.batch_sweep(b)
+        for p in single:
+            bfc.sweep(p)
+        for p, q in zip(single, batched):
+            assert np.array_equal(bfc.get_cores(p).cpu().numpy(), bfc.get_cores(q).cpu().numpy())
+        b.close()
+        for p in single + batched:
+            p.close()
+
+
+def test_autotune_restores_cores_and_applies_choice():
+    ws = [make_workload(**s) for s in batched_instances(64)[14:20]]  # n = 1024 and 2048
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        probs = [_make(w, "c64") for w in ws]
+        bfc.batch_sweep(bfc.batch_create(probs))
+        before = [bfc.get_cores(p).cpu().numpy() for p in probs]
+        chosen, ms = bfc.autotune_item_size(probs, sweeps=2, candidates=(64, 128, 256))
+        assert chosen in (64, 128, 256)
+        assert all(v > 0 for v in ms.values()) and ms[chosen] == min(ms.values())
+        after = [bfc.get_cores(p).cpu().numpy() for p in probs]
+        for x, y in zip(before, after):
+            assert np.array_equal(x, y)
+        # the tuned problems sweep like fresh ones given the same item size
+        fresh = [_make(w, "c64") for w in ws]
+        bfc.batch_sweep(bfc.batch_create(fresh))
+        for p in fresh:
+            bfc.set_item_size(p, chosen)
+        for p, q in zip(probs, fresh):
+            bfc.sweep(p)
+            bfc.sweep(q)
+            assert np.array_equal(bfc.get_cores(p).cpu().numpy(), bfc.get_cores(q).cpu().numpy())
+        for p in probs + fresh:
+            p.close()
