@@ -347,6 +347,9 @@ def batched_record(bfc, torch, dev, steps):
 
     t_batch = timed(lambda: bfc.batch_sweep(b), steps)
     t_each = timed(lambda: [bfc.sweep(p) for p in probs], steps)
+    # tile shape chosen by the autotuner (cores restored after its trials)
+    chosen, trials = bfc.autotune_item_size(probs, sweeps=2, candidates=(64, 128, 256, 512))
+    t_tuned = timed(lambda: bfc.batch_sweep(b), steps)
     res = bfc.batch_residuals(b)
     worst = max((num / den) ** 0.5 for num, den in res)
     b.close()
@@ -360,6 +363,10 @@ def batched_record(bfc, torch, dev, steps):
                     "ms_per_sweep": round(1e3 * t_batch, 4)},
         "one_by_one": {"value": round(total / t_each, 1), "unit": "entries/s",
                        "ms_per_sweep": round(1e3 * t_each, 4)},
+        "batched_autotuned": {"value": round(total / t_tuned, 1), "unit": "entries/s",
+                              "ms_per_sweep": round(1e3 * t_tuned, 4),
+                              "item_size": chosen,
+                              "trials_ms_per_sweep": {str(k): round(v, 4) for k, v in trials.items()}},
         "speedup": round(t_each / t_batch, 3),
         "worst_train_rel_err_after": worst,
     }
