@@ -928,22 +928,47 @@ struct EnvArgs {
   cx<T>* out;
 };
 
+// Nodes are sorted so that neighbours mostly multiply the same core slice.
+// When every node of a wavefront does, the wavefront stages that slice in LDS
+// once (36 or 64 values) instead of each lane streaming it through L1.
 template <typename T, int R, int RIGHT>
 __device__ __attribute__((always_inline)) inline void env_level_body(const EnvArgs<T>& a,
                                                                      int blk) {
+  __shared__ cx<T> zs[4][R * R];  // one slice per wavefront of the 256-thread block
   const int k = blk * 256 + (int)threadIdx.x;
-  if (k >= a.count) return;
-  const uint32_t na = (uint32_t)a.node_a[k], nb = (uint32_t)a.node_b[k];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool live = k < a.count;
+  // lane 0 holds the wavefront's first node: no live lane without it
+  if (__builtin_amdgcn_readfirstlane(live ? 1 : 0) == 0) return;
   const int L = a.L, p = a.p;
+  uint32_t key = 0, na = 0, nb = 0;
   cx<T> v[R];
-  load_env<T, R>(a.parent_vec, a.parent[k], v);
-  if (RIGHT) {
-    const uint32_t key = (na << (p + 1)) | ((nb / (uint32_t)a.c) >> (L - p - 1));
-    mat_vec<T, R>(a.cores + inner_off(a.n, L, R, p + 1) + (int64_t)key * R * R, v);
-  } else {
-    const uint32_t key = (((nb / (uint32_t)a.c) >> (p - 2)) << (p - 1)) | na;
-    vec_mat<T, R>(v, a.cores + inner_off(a.n, L, R, p - 1) + (int64_t)key * R * R);
+  if (live) {
+    na = (uint32_t)a.node_a[k];
+    nb = (uint32_t)a.node_b[k];
+    key = RIGHT ? (na << (p + 1)) | ((nb / (uint32_t)a.c) >> (L - p - 1))
+                : (((nb / (uint32_t)a.c) >> (p - 2)) << (p - 1)) | na;
+    load_env<T, R>(a.parent_vec, a.parent[k], v);
   }
+  const cx<T>* Zcore = a.cores + inner_off(a.n, L, R, RIGHT ? p + 1 : p - 1);
+  const uint32_t k0 = __builtin_amdgcn_readfirstlane(key);
+  const bool uniform = __ballot(live && key != k0) == 0;
+  if (uniform) {
+    const cx<T>* src = Zcore + (int64_t)k0 * R * R;
+    for (int e = lane; e < R * R; e += 64) zs[wave][e] = src[e];
+    wave_sync();
+    if (RIGHT)
+      mat_vec<T, R>(zs[wave], v);
+    else
+      vec_mat<T, R>(v, zs[wave]);
+  } else {
+    const cx<T>* Z = Zcore + (int64_t)key * R * R;
+    if (RIGHT)
+      mat_vec<T, R>(Z, v);
+    else
+      vec_mat<T, R>(v, Z);
+  }
+  if (!live) return;
   cx<T>* o = a.out + (int64_t)k * R;
 #pragma unroll
   for (int q = 0; q < R; ++q) o[q] = v[q];
