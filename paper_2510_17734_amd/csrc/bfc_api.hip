@@ -187,6 +187,9 @@ bfc_status bfc_init_cores(const bfc_config* cfg, int64_t nnz, const int32_t* d_r
     return fail(BFC_EHIP);
   }
   if ((s = build_layout(P, d_rows, d_cols, d_vals, st)) != BFC_OK) return fail(s);
+  if ((s = dev_alloc(P, (void**)&P->fused_res, 2 * sizeof(double) * P->lay[P->L + 1].nblocks)) !=
+      BFC_OK)
+    return fail(s);
   if (P->max_items > 0) {
     P->partials_bytes = (size_t)P->max_items * inner_partial_bytes(P->prec, P->r);
     if ((s = dev_alloc(P, &P->partials, P->partials_bytes)) != BFC_OK) return fail(s);
@@ -247,8 +250,10 @@ static bfc_status sweep_via_graph(bfc_problem* p, hipStream_t st) {
     BFC_HIP_TRY(hipGraphInstantiate(&p->sweep_exec, g, nullptr, nullptr, 0));
   }
   BFC_HIP_TRY(hipGraphLaunch(p->sweep_exec, st));
+  // the state a sweep leaves (host-side bookkeeping the replay does not run)
   for (auto& E : p->rlev) E.valid = false;
   for (size_t q = 2; q < p->llev.size(); ++q) p->llev[q].valid = true;
+  p->fused_res_valid = true;
   return BFC_OK;
 }
 
@@ -476,6 +481,7 @@ void free_batch_plan(Batch* B) {
   B->allocs.assign(1, B->res);
   B->sweep.clear();
   B->resid.clear();
+  B->resid_fused.clear();
 }
 }  // namespace bfc
 
@@ -584,6 +590,7 @@ bfc_status bfc_batch_sweep(bfc_batch* b, void* hip_stream) {
   for (bfc::Problem* P : b->probs) {
     for (auto& E : P->rlev) E.valid = false;
     for (size_t q = 2; q < P->llev.size(); ++q) P->llev[q].valid = true;
+    P->fused_res_valid = true;
   }
   return BFC_OK;
 }
@@ -596,14 +603,20 @@ bfc_status bfc_batch_residuals(bfc_batch* b, double* out_sq, void* hip_stream) {
   hipStream_t st = (hipStream_t)hip_stream;
   BFC_TRY(refresh_batch(b));
   const size_t k = b->probs.size();
-  // the residuals read the last left level of every problem: bring stale ones
-  // up to date (a no-op right after a batched sweep)
-  for (bfc::Problem* P : b->probs) {
-    bool stale = false;
-    for (int q = 2; q <= P->L + 1; ++q) stale = stale || !P->llev[q].valid;
-    if (stale) BFC_TRY(launch_residual_observed(P, P->red + P->red_len, st));
+  // right after a (batched) sweep the last core's update has left per-fiber
+  // norms; otherwise the residual reads the last left level of every problem
+  bool fused = true;
+  for (bfc::Problem* P : b->probs) fused = fused && P->fused_res_valid;
+  if (fused) {
+    BFC_TRY(launch_batch(b->resid_fused, b->prec, st));
+  } else {
+    for (bfc::Problem* P : b->probs) {
+      bool stale = false;
+      for (int q = 2; q <= P->L + 1; ++q) stale = stale || !P->llev[q].valid;
+      if (stale) BFC_TRY(launch_residual_observed(P, P->red + P->red_len, st));
+    }
+    BFC_TRY(launch_batch(b->resid, b->prec, st));
   }
-  BFC_TRY(launch_batch(b->resid, b->prec, st));
   BFC_HIP_TRY(hipMemcpyAsync(b->res_host, b->res, 2 * sizeof(double) * k, hipMemcpyDeviceToHost,
                              st));
   std::vector<int32_t> nfail(k, 0);

@@ -159,6 +159,8 @@ struct Problem {
   double* ir_lam = nullptr;
   void* ir_old = nullptr;
   double* red = nullptr;             // residual reduction scratch
+  double* fused_res = nullptr;       // 2 per fiber of the last core: residual norms
+  bool fused_res_valid = false;      // fused_res belongs to the current cores
   size_t red_len = 0;
   double* red_host = nullptr;        // pinned, 2 doubles
   std::vector<void*> allocs;         // everything hipMalloc'd
@@ -181,7 +183,7 @@ bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes);
 // per problem taking part) whose argument structs and block prefix table live
 // in device memory.
 enum { BK_ENV_RIGHT = 0, BK_ENV_LEFT = 1, BK_OUTER = 2, BK_GRAM_ROW = 3, BK_GRAM_COL = 4,
-       BK_SOLVE = 5, BK_RES = 6, BK_RES_FINAL = 7 };
+       BK_SOLVE = 5, BK_RES = 6, BK_RES_FINAL = 7, BK_RES_FUSED = 8 };
 struct BatchLaunch {
   int kind = 0, r = 0;
   void* tasks = nullptr;        // device array of argument structs
@@ -198,6 +200,7 @@ struct Batch {
   int prec = BFC_C64;
   std::vector<BatchLaunch> sweep;  // one sweep of every problem, in dependency order
   std::vector<BatchLaunch> resid;  // observed-set residual norms of every problem
+  std::vector<BatchLaunch> resid_fused;  // the same from the last core's per-fiber sums
   double* res = nullptr;           // device, 2 per problem
   double* res_host = nullptr;      // pinned, 2 per problem
   std::vector<void*> allocs;       // device memory of the plan

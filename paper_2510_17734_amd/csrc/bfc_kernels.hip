@@ -178,6 +178,63 @@ __device__ inline double2 inner_h(const double* S, int W, int row) {
 // outer cores: 16 lanes (one DPP row) per fiber, fused serial solve
 // ---------------------------------------------------------------------------
 constexpr int kOuterThreads = 256;
+// blocks of an outer-core launch: 16 lanes per fiber
+inline int outer_grid(const CoreLayout& C) {
+  return (int)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
+}
+
+// Regularized r x r solve of one fiber from its real-coordinate Gram (acc)
+// and right-hand side (hx, hy); writes the fiber, or keeps it and counts a
+// failure when no rung of the regularization ladder is positive definite.
+template <typename T, int R>
+__device__ __attribute__((always_inline)) inline void outer_fiber_solve(
+    const T (&acc)[R * R], const T (&hx)[R], const T (&hy)[R], double reg_rel, double reg_floor,
+    int prox, int32_t* flags, cx<T>* fiber) {
+  // K[a][a2] from the real coordinates; trace; regularization ladder
+  double tr = 0.0;
+#pragma unroll
+  for (int a = 0; a < R; ++a) tr += (double)acc[a * R + a];
+  const double tau = tr / R;
+  const double unit = fmax(reg_floor, 0x1p-53);
+  double lam = fmax(reg_rel, R * reg_floor) * tau;
+  double2 M[R][R];
+  bool ok = false;
+  int attempt = 0;
+  for (; attempt < 4; ++attempt) {
+    if (attempt > 0) {
+      if (!(lam > 0.0)) break;
+      lam = fmax(100.0 * lam, R * unit * tau);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        int re, im, sg;
+        herm_coord(i, j, R, re, im, sg);
+        M[i][j] = make_double2((double)acc[re], im >= 0 ? sg * (double)acc[im] : 0.0);
+        if (i == j) M[i][j].x += lam;
+      }
+    ok = serial_cholesky<R>(M);
+    if (ok) break;
+  }
+  if (!ok) {
+    atomicAdd(flags, 1);
+    return;
+  }
+  if (attempt > 0) atomicAdd(flags + 1, 1);
+  double2 sol[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    sol[k] = make_double2((double)hx[k], (double)hy[k]);
+    if (prox) {
+      sol[k].x += lam * (double)fiber[k].x;
+      sol[k].y += lam * (double)fiber[k].y;
+    }
+  }
+  serial_chol_solve<R>(M, sol);
+#pragma unroll
+  for (int k = 0; k < R; ++k) fiber[k] = {T(sol[k].x), T(sol[k].y)};
+}
 
 template <typename T>
 struct OuterArgs {
@@ -191,6 +248,7 @@ struct OuterArgs {
   double reg_floor;
   int prox;
   int32_t* flags;
+  double* res_partial;  // per block: residual norms after the update, or null
 };
 
 template <typename T, int R>
@@ -248,52 +306,62 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
     hx[k] = row16_sum(hx[k]);
     hy[k] = row16_sum(hy[k]);
   }
-  if (sub != 0 || b >= nblocks || e0 == e1) return;  // empty fiber: keep it
-  // K[a][a2] from the real coordinates; trace; regularization ladder
-  double tr = 0.0;
+  // the solve, by lane 0 of the fiber's row; z ends as the fiber's value
+  cx<T> z[R];
 #pragma unroll
-  for (int a = 0; a < R; ++a) tr += (double)acc[a * R + a];
-  const double tau = tr / R;
-  const double unit = fmax(reg_floor, 0x1p-53);
-  double lam = fmax(reg_rel, R * reg_floor) * tau;
-  cx<T>* fiber = fibers + (int64_t)b * R;
-  double2 M[R][R];
-  bool ok = false;
-  int attempt = 0;
-  for (; attempt < 4; ++attempt) {
-    if (attempt > 0) {
-      if (!(lam > 0.0)) break;
-      lam = fmax(100.0 * lam, R * unit * tau);
-    }
+  for (int k = 0; k < R; ++k) z[k] = cx<T>{T(0), T(0)};
+  if (sub == 0 && b < nblocks) {
+    cx<T>* fiber = fibers + (int64_t)b * R;
+    if (e0 != e1)  // empty fiber: keep it
+      outer_fiber_solve<T, R>(acc, hx, hy, reg_rel, reg_floor, prox, flags, fiber);
 #pragma unroll
-    for (int i = 0; i < R; ++i)
-#pragma unroll
-      for (int j = 0; j <= i; ++j) {
-        int re, im, sg;
-        herm_coord(i, j, R, re, im, sg);
-        M[i][j] = make_double2((double)acc[re], im >= 0 ? sg * (double)acc[im] : 0.0);
-        if (i == j) M[i][j].x += lam;
-      }
-    ok = serial_cholesky<R>(M);
-    if (ok) break;
+    for (int k = 0; k < R; ++k) z[k] = fiber[k];
   }
-  if (!ok) {
-    atomicAdd(flags, 1);
-    return;
-  }
-  if (attempt > 0) atomicAdd(flags + 1, 1);
-  double2 sol[R];
+  if (!A.res_partial) return;  // the same for the whole launch
+  // residual norms of the updated fiber over its entries: x_e = a_e . z
+  const int src = (int)(threadIdx.x & 63) & ~15;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    sol[k] = make_double2((double)hx[k], (double)hy[k]);
-    if (prox) {
-      sol[k].x += lam * (double)fiber[k].x;
-      sol[k].y += lam * (double)fiber[k].y;
+    z[k].x = __shfl(z[k].x, src);
+    z[k].y = __shfl(z[k].y, src);
+  }
+  double r0 = 0.0, r1 = 0.0;
+  for (int base = e0 + sub; base < e1; base += 16 * 4) {
+    int id[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) id[q] = (base + 16 * q < e1) ? env_idx[base + 16 * q] : -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (id[q] < 0) continue;
+      const cx<T> t = vals[base + 16 * q];
+      cx<T> v[R];
+      load_env<T, R>(env, id[q], v);
+      cx<T> x = {T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < R; ++k) cfma(x, v[k], z[k]);
+      const double dx = (double)t.x - (double)x.x, dy = (double)t.y - (double)x.y;
+      r0 += dx * dx + dy * dy;
+      r1 += (double)t.x * (double)t.x + (double)t.y * (double)t.y;
     }
   }
-  serial_chol_solve<R>(M, sol);
-#pragma unroll
-  for (int k = 0; k < R; ++k) fiber[k] = {T(sol[k].x), T(sol[k].y)};
+  r0 = row16_sum(r0);
+  r1 = row16_sum(r1);
+  // the block's 16 fibers summed in a fixed order: one pair per block
+  __shared__ double fr[2 * (kOuterThreads / 16)];
+  if (sub == 0) {
+    fr[2 * (threadIdx.x >> 4)] = r0;
+    fr[2 * (threadIdx.x >> 4) + 1] = r1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int f = 0; f < kOuterThreads / 16; ++f) {
+      s0 += fr[2 * f];
+      s1 += fr[2 * f + 1];
+    }
+    A.res_partial[2 * blk] = s0;
+    A.res_partial[2 * blk + 1] = s1;
+  }
 }
 
 template <typename T, int R>
@@ -1197,9 +1265,10 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
     {
       ProfScope ps(&P->prof, KIND_OUTER, st);
       const unsigned grid = (unsigned)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
+      // the last core's update also leaves the train residual's per-fiber norms
       outer_update_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(OuterArgs<T>{
           fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks, reg, floor_, prox,
-          P->flags});
+          P->flags, p == L + 1 ? P->fused_res : nullptr});
     }
     BFC_HIP_TRY(hipGetLastError());
   } else {
@@ -1260,6 +1329,7 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
       }
     }
   }
+  P->fused_res_valid = (p == L + 1);
   // core p changed: right levels below it and left levels above it are stale
   for (int q = 0; q < p && q < L; ++q) P->rlev[q].valid = false;
   for (int q = p + 1; q <= L + 1; ++q)
@@ -1280,6 +1350,14 @@ inline void residual_split(const Problem* P, int64_t m, int64_t& per, int64_t& n
 template <typename T, int R>
 bfc_status residual_observed_t(Problem* P, double* out2, hipStream_t st) {
   const int L = P->L;
+  if (P->fused_res_valid) {
+    // the last core's update left per-fiber norms for exactly these cores
+    ProfScope ps(&P->prof, KIND_RESIDUAL, st);
+    residual_final_kernel<<<1, kResThreads, 0, st>>>(P->fused_res, outer_grid(P->lay[L + 1]),
+                                                      out2);
+    BFC_HIP_TRY(hipGetLastError());
+    return BFC_OK;
+  }
   BFC_TRY(ensure_left<T, R>(P, L + 1, st));
   cx<T>* cores = (cx<T>*)P->cores;
   const CoreLayout& C = P->lay[L + 1];
@@ -1411,7 +1489,10 @@ bfc_status upload_tasks(Batch* B, int kind, int r, const std::vector<A>& args,
   BFC_HIP_TRY(hipMemcpy(bl.tasks, args.data(), sizeof(A) * args.size(), hipMemcpyHostToDevice));
   BFC_HIP_TRY(hipMemcpy(bl.block_off, off.data(), sizeof(int32_t) * off.size(),
                         hipMemcpyHostToDevice));
-  (kind == BK_RES || kind == BK_RES_FINAL ? B->resid : B->sweep).push_back(bl);
+  (kind == BK_RES || kind == BK_RES_FINAL   ? B->resid
+   : kind == BK_RES_FUSED                   ? B->resid_fused
+                                            : B->sweep)
+      .push_back(bl);
   return BFC_OK;
 }
 
@@ -1444,7 +1525,8 @@ struct BatchStep {
     }
     a.push_back(OuterArgs<T>{fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks,
                              P->cfg.reg_rel, reg_floor_of(P),
-                             P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0, P->flags});
+                             P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0, P->flags,
+                             p == L + 1 ? P->fused_res : nullptr});
     b.push_back(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
   }
   static void inner(const Problem* P, int p, std::vector<GramArgs<T>>& grow,
@@ -1539,7 +1621,15 @@ struct BatchPlanR {
       one.push_back(1);
     }
     BFC_TRY(upload_tasks<T>(B, BK_RES, R, a, b));
-    return upload_tasks<T>(B, BK_RES_FINAL, R, f, one);
+    BFC_TRY(upload_tasks<T>(B, BK_RES_FINAL, R, f, one));
+    // the same norms from the per-fiber sums the last core's update leaves
+    std::vector<ResFinalArgs> fz;
+    for (Problem* P : ps) {
+      size_t k = 0;
+      while (B->probs[k] != P) ++k;
+      fz.push_back(ResFinalArgs{P->fused_res, outer_grid(P->lay[P->L + 1]), B->res + 2 * k});
+    }
+    return upload_tasks<T>(B, BK_RES_FUSED, R, fz, one);
   }
 };
 
@@ -1612,6 +1702,7 @@ bfc_status launch_batched_r(const BatchLaunch& bl, hipStream_t st) {
           (const ResObsArgs<T>*)bl.tasks, bl.block_off, bl.ntasks);
       break;
     case BK_RES_FINAL:
+    case BK_RES_FUSED:
       residual_final_batched<<<bl.ntasks, kResThreads, 0, st>>>((const ResFinalArgs*)bl.tasks);
       break;
   }
@@ -1672,6 +1763,7 @@ bfc_status launch_residual_observed(Problem* P, double* out2, hipStream_t st) {
 void invalidate_envs(Problem* P) {
   for (auto& E : P->rlev) E.valid = false;
   for (auto& E : P->llev) E.valid = false;
+  P->fused_res_valid = false;
 }
 
 bfc_status launch_convert_cores(Problem* P, const void* src, void* dst, bool to_internal,
