@@ -115,8 +115,10 @@ int64_t bfc_num_params(int64_t n, int32_t L, int32_t r);
  *
  * Regularization used by every later core update: with tau = trace(K)/d,
  * lam = max(reg_rel, d * u_K) * tau where u_K is the unit roundoff of the
- * Gram accumulation (0 in BFC_C128, 2^-24 in the complex64 modes, so that
- * FP32 rounding cannot make K + lam I indefinite).  If the FP64 Cholesky
+ * Gram accumulation (0 in BFC_C128; 2^-20 for the FP32-accumulated Grams of
+ * the complex64 modes: the FP32 unit roundoff 2^-24 times the sqrt(256)
+ * growth of the sums forming them; 2^-10 for the inner Grams of
+ * BFC_C64_BF16GRAM), so that rounding cannot make K + lam I indefinite.  If the FP64 Cholesky
  * factorization still fails while lam > 0, lam is raised to
  * max(100 lam, d max(u_K, 2^-53) tau), at most three times.
  * Returns EINVAL for nnz < 1, a bad config (n not c*2^L, r or L out of

@@ -36,8 +36,9 @@ design notes):
   (K + lam I) s = y + lam s_old with lam = max(reg_rel, d * reg_floor) *
   trace(K) / d, d the block's unknown count; ``proximal=False`` gives plain
   ridge (y on the right).  ``reg_floor`` is the unit roundoff of the
-  arithmetic that formed K (0 for an exact K; 2^-24 when K is accumulated in
-  FP32), so that rounding cannot make the system indefinite.  Should the
+  arithmetic that formed K (0 for an exact K; callers comparing with an
+  FP32-accumulated K pass that rounding level), so that rounding cannot make
+  the system indefinite.  Should the
   Cholesky factorization still fail while lam > 0, lam is raised to
   max(100 lam, d u trace(K)/d), u = max(reg_floor, 2^-53), up to three times;
   after that (or at once when lam = 0) the block is reported as not positive

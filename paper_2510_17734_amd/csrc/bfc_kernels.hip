@@ -588,11 +588,18 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // BF16-Gram mode: regularization floor of the inner solves and refinement
 // steps.  A bf16-formed Gram differs from the exact one by up to ~2^-8 of its
 // entries; refinement with that factor contracts only where lam dominates the
-// difference.  At a floor of 2^-8 every update refines to within ~1e-5 of the
-// regularized optimum but the damping slows the sweeps; at 2^-12 one step
-// leaves updates within ~1e-2 of it and the sweeps converge nearly as fast as
-// with the FP32 Gram (measured on the Green's-function workloads).
-constexpr double kBf16RegFloor = 0x1p-12;
+// difference, and where it does not, it amplifies the error (more steps make
+// it worse).  Measured on the Green's-function workloads: at 2^-12 single
+// updates can raise the objective (train error +25% in one sweep), at 2^-10
+// every sweep descends, at 2^-8 too but the damping slows convergence.
+constexpr double kBf16RegFloor = 0x1p-10;
+// Regularization floor of the FP32-accumulated Grams: the FP32 unit roundoff
+// 2^-24 times the sqrt(256) growth of the sums that form them (at most 8
+// entries per subgroup, then up to 128 subgroups per MFMA chain and per
+// outer-fiber lane).  At 2^-24 itself the long-run sweeps drift along
+// directions the data leave undetermined until the cores overflow (about 40
+// sweeps on the Green's-function workloads); at 2^-20 they stay bounded.
+constexpr double kF32RegFloor = 0x1p-20;
 constexpr int kBf16IrSteps = 1;
 constexpr int kBfLd = 64 + 8;  // subgroups per staged coordinate row, padded
 
@@ -1244,7 +1251,7 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   const int L = P->L;
   const bool outer = p == 0 || p == L + 1;  // outer Grams are FP32 in both complex64 modes
   const double floor_ = P->prec == BFC_C128             ? 0.0
-                        : (P->prec == BFC_C64 || outer) ? 0x1p-24
+                        : (P->prec == BFC_C64 || outer) ? kF32RegFloor
                                                         : kBf16RegFloor;
   const int prox = P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0;
   {
@@ -1496,7 +1503,7 @@ bfc_status upload_tasks(Batch* B, int kind, int r, const std::vector<A>& args,
   return BFC_OK;
 }
 
-inline double reg_floor_of(const Problem* P) { return P->prec == BFC_C128 ? 0.0 : 0x1p-24; }
+inline double reg_floor_of(const Problem* P) { return P->prec == BFC_C128 ? 0.0 : kF32RegFloor; }
 
 template <typename T, int R>
 struct BatchStep {

@@ -30,7 +30,7 @@ def _gpu_cores(prob, w):
     return bfc.unflatten_cores(bfc.get_cores(prob).cpu().numpy(), w.n, w.L, w.r)
 
 
-FLOORS = {"c128": 0.0, "c64": 2.0 ** -24, "bf16gram": 2.0 ** -12}
+FLOORS = {"c128": 0.0, "c64": 2.0 ** -20, "bf16gram": 2.0 ** -10}
 
 
 def _sampled_check(w, precision, sweeps_before=0, cores=None):
