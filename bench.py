@@ -201,6 +201,8 @@ KIND_PATTERNS = (("inner_gram", "inner_gram_kernel"), ("inner_solve", "inner_sol
 
 
 def kernel_kind(name):
+    if "batched" in name:  # batched launches belong to the batching workload
+        return None
     for kind, pat in KIND_PATTERNS:
         if pat in name:
             return kind
