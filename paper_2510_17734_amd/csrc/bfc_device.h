@@ -211,55 +211,57 @@ __device__ __attribute__((always_inline)) inline double rsqrt_nr(double x) {
 }
 
 // Factor the nb x nb lower diagonal block at (k0, k0) of M and return the
-// inverse of its factor in Di (lower triangular; rows and columns >= nb are
-// the identity).  False if a pivot is not positive; every thread reads the
-// same values and reaches the same answer.
+// inverse of its factor: dg receives the (real) diagonal of L_BB^-1 and
+// Di[i][j], i > j, its strictly lower part (rows and columns >= nb are the
+// identity).  The diagonal of a Hermitian matrix and of its Cholesky factor
+// is real, so only the real parts of pivots are formed and products with
+// diagonal entries are real scalings.  False if a pivot is not positive;
+// every thread reads the same values and reaches the same answer.
 __device__ __attribute__((always_inline)) inline bool diag_block_inverse(
-    const double2* M, int ld, int k0, int nb, double2 (&Di)[kNb][kNb]) {
+    const double2* M, int ld, int k0, int nb, double (&dg)[kNb], double2 (&Di)[kNb][kNb]) {
   double2 D[kNb][kNb];
+  double dd[kNb];
 #pragma unroll
-  for (int a = 0; a < kNb; ++a)
+  for (int a = 0; a < kNb; ++a) {
+    dd[a] = (a < nb) ? M[(k0 + a) * ld + k0 + a].x : 1.0;
 #pragma unroll
-    for (int b = 0; b <= a; ++b)
-      D[a][b] = (a < nb) ? M[(k0 + a) * ld + k0 + b] : make_double2(a == b ? 1.0 : 0.0, 0.0);
-  double inv[kNb];
+    for (int b = 0; b < a; ++b)
+      D[a][b] = (a < nb) ? M[(k0 + a) * ld + k0 + b] : make_double2(0.0, 0.0);
+  }
 #pragma unroll
   for (int k = 0; k < kNb; ++k) {
-    const double piv = D[k][k].x;
-    if (!(piv > 0.0)) return false;
-    inv[k] = rsqrt_nr(piv);  // 1 / L[k][k]
+    if (!(dd[k] > 0.0)) return false;
+    dg[k] = rsqrt_nr(dd[k]);  // 1 / L[k][k]
 #pragma unroll
     for (int i = k + 1; i < kNb; ++i) {
-      D[i][k].x *= inv[k];
-      D[i][k].y *= inv[k];
+      D[i][k].x *= dg[k];
+      D[i][k].y *= dg[k];
     }
 #pragma unroll
-    for (int j = k + 1; j < kNb; ++j)
+    for (int j = k + 1; j < kNb; ++j) {
+      dd[j] = fma(-D[j][k].x, D[j][k].x, fma(-D[j][k].y, D[j][k].y, dd[j]));
 #pragma unroll
-      for (int i = j; i < kNb; ++i) {
+      for (int i = j + 1; i < kNb; ++i) {
         const double2 t = cmul_conj(D[i][k], D[j][k]);
         D[i][j].x -= t.x;
         D[i][j].y -= t.y;
       }
+    }
   }
-  // Di[i][j] = -inv[i] * sum_{k=j}^{i-1} D[i][k] Di[k][j]
+  // Di[i][j] = -dg[i] * (L[i][j] dg[j] + sum_{k=j+1}^{i-1} L[i][k] Di[k][j])
 #pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-#pragma unroll
-    for (int i = 0; i < j; ++i) Di[i][j] = make_double2(0.0, 0.0);
-    Di[j][j] = make_double2(inv[j], 0.0);
+  for (int j = 0; j < kNb; ++j)
 #pragma unroll
     for (int i = j + 1; i < kNb; ++i) {
-      double2 s = make_double2(0.0, 0.0);
+      double2 s = make_double2(D[i][j].x * dg[j], D[i][j].y * dg[j]);
 #pragma unroll
-      for (int k = j; k < i; ++k) {
+      for (int k = j + 1; k < i; ++k) {
         const double2 t = cmul(D[i][k], Di[k][j]);
         s.x += t.x;
         s.y += t.y;
       }
-      Di[i][j] = make_double2(-inv[i] * s.x, -inv[i] * s.y);
+      Di[i][j] = make_double2(-dg[i] * s.x, -dg[i] * s.y);
     }
-  }
   return true;
 }
 
@@ -288,8 +290,9 @@ __device__ __attribute__((always_inline)) inline bool wg_cholesky(double2* M, in
 #pragma unroll 1
   for (int k0 = 0; k0 < d; k0 += kNb) {
     const int nb = d - k0 < kNb ? d - k0 : kNb;
+    double dg[kNb];
     double2 Di[kNb][kNb];
-    if (!diag_block_inverse(M, ld, k0, nb, Di)) return false;
+    if (!diag_block_inverse(M, ld, k0, nb, dg, Di)) return false;
     const int r0 = k0 + nb, m = d + 1 - r0;  // rows below the block, border included
     for (int t = tid; t < m; t += NT) {
       double2* row = M + (r0 + t) * ld + k0;
@@ -297,10 +300,10 @@ __device__ __attribute__((always_inline)) inline bool wg_cholesky(double2* M, in
 #pragma unroll
       for (int q = 0; q < kNb; ++q) a[q] = q < nb ? row[q] : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < kNb; ++q) {  // L_i[q] = sum_{p<=q} a[p] conj(Di[q][p])
-        double2 l = make_double2(0.0, 0.0);
+      for (int q = 0; q < kNb; ++q) {  // L_i[q] = a[q] dg[q] + sum_{p<q} a[p] conj(Di[q][p])
+        double2 l = make_double2(a[q].x * dg[q], a[q].y * dg[q]);
 #pragma unroll
-        for (int p = 0; p <= q; ++p) {
+        for (int p = 0; p < q; ++p) {
           const double2 s = cmul_conj(a[p], Di[q][p]);
           l.x += s.x;
           l.y += s.y;
@@ -309,12 +312,14 @@ __device__ __attribute__((always_inline)) inline bool wg_cholesky(double2* M, in
         panel[(r0 + t) * kPanelLd + q] = l;
       }
     }
-    if (tid < kNb * kNb) {
+    if (tid == 0) {  // the full block L_BB^-1 for the triangular solves
 #pragma unroll
       for (int a = 0; a < kNb; ++a)
 #pragma unroll
         for (int b = 0; b < kNb; ++b)
-          if (tid == a * kNb + b) dinv[k0 * kNb + tid] = Di[a][b];
+          dinv[k0 * kNb + a * kNb + b] = a == b  ? make_double2(dg[a], 0.0)
+                                         : a > b ? Di[a][b]
+                                                 : make_double2(0.0, 0.0);
     }
     __syncthreads();
     // lower triangle of the trailing rows; the border's own diagonal entry
@@ -363,10 +368,11 @@ __device__ __attribute__((always_inline)) inline void wave_back_solve(const doub
       bb[q] = q < nb ? make_double2(bcast_d(b.x, k0 + q), bcast_d(b.y, k0 + q))
                      : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int q = 0; q < kNb; ++q) {  // s[q] = sum_{p>=q} conj(Di[p][q]) bb[p]
-      s[q] = make_double2(0.0, 0.0);
+    for (int q = 0; q < kNb; ++q) {  // s[q] = sum_{p>=q} conj(Di[p][q]) bb[p], Di[q][q] real
+      const double dq = Di[q * kNb + q].x;
+      s[q] = make_double2(bb[q].x * dq, bb[q].y * dq);
 #pragma unroll
-      for (int p = q; p < kNb; ++p) {
+      for (int p = q + 1; p < kNb; ++p) {
         const double2 t = cmul_conj(bb[p], Di[p * kNb + q]);
         s[q].x += t.x;
         s[q].y += t.y;
