@@ -61,6 +61,35 @@ __device__ inline void load_env(const cx<T>* __restrict__ src, int idx, cx<T> (&
   for (int a = 0; a < R; ++a) v[a] = p[a];
 }
 
+// Marks a loaded value as used here.  Placed after a group of loads, it keeps
+// the compiler from moving any of them into the conditional code that
+// consumes it: every load of the group is in flight before the first wait,
+// so the group costs one memory latency instead of one per load.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void pin(cx<T>& v) {
+  asm volatile("" : "+v"(v.x), "+v"(v.y));
+}
+
+// Environment vectors and values of G entries, loaded as one group.  An absent
+// entry (id < 0) reads vector 0 and value 0 (both exist whenever the kernel
+// runs) and must be skipped by the caller.
+template <typename T, int R, int G>
+__device__ __attribute__((always_inline)) inline void gather_group(
+    const cx<T>* __restrict__ src, const cx<T>* __restrict__ vals, const int (&id)[G],
+    const int (&ent)[G], cx<T> (&v)[G][R], cx<T> (&t)[G]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    load_env<T, R>(src, id[g] >= 0 ? id[g] : 0, v[g]);
+    t[g] = vals[id[g] >= 0 ? ent[g] : 0];
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int a = 0; a < R; ++a) pin(v[g][a]);
+    pin(t[g]);
+  }
+}
+
 // v <- v * Z   (row vector times an R x R slice)
 template <typename T, int R>
 __device__ inline void vec_mat(cx<T> (&v)[R], const cx<T>* __restrict__ Z) {

@@ -381,6 +381,9 @@ __global__ __launch_bounds__(kOuterThreads) void outer_update_kernel_batched(con
 // ---------------------------------------------------------------------------
 // inner cores: Gram/RHS partial products per work item (one wavefront)
 // ---------------------------------------------------------------------------
+// entries of a subgroup whose environment loads are in flight together
+constexpr int kGatherGroup = 4;
+
 template <int R>
 struct InnerGeom {
   static constexpr int D = R * R;
@@ -418,26 +421,38 @@ __device__ __attribute__((always_inline)) inline void subgroup_rows(
       load_env<T, R>(lenv, lidx[e0], shared_env);
     else
       load_env<T, R>(renv, ridx[e0], shared_env);
-    // a subgroup holds at most kSubgroup entries: issue every index load,
-    // then every vector load, then compute
+  }
+  {
+    // a subgroup holds at most kSubgroup entries: every index load first
     const int32_t* eidx = BYROW ? ridx : lidx;
     const cx<T>* esrc = BYROW ? renv : lenv;
     int id[kSubgroup];
 #pragma unroll
     for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
+    // entries in groups of G whose vector loads are issued together; a group
+    // that no lane of the wavefront needs is skipped
 #pragma unroll
-    for (int q = 0; q < kSubgroup; ++q) {
-      if (id[q] < 0) continue;
-      const cx<T> t = vals[e0 + q];
-      cx<T> v[R];
-      load_env<T, R>(esrc, id[q], v);
-      herm_acc<T, R>(sum, v);
+    for (int g0 = 0; g0 < kSubgroup; g0 += kGatherGroup) {
+      if (__ballot(e0 + g0 < e1) == 0) break;
+      int gid[kGatherGroup], ent[kGatherGroup];
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        cx<T> h = {yx[k], yy[k]};
-        cfma_conj(h, v[k], t);
-        yx[k] = h.x;
-        yy[k] = h.y;
+      for (int g = 0; g < kGatherGroup; ++g) {
+        gid[g] = id[g0 + g];
+        ent[g] = e0 + g0 + g;
+      }
+      cx<T> v[kGatherGroup][R], t[kGatherGroup];
+      gather_group<T, R, kGatherGroup>(esrc, vals, gid, ent, v, t);
+#pragma unroll
+      for (int g = 0; g < kGatherGroup; ++g) {
+        if (gid[g] < 0) continue;
+        herm_acc<T, R>(sum, v[g]);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          cx<T> h = {yx[k], yy[k]};
+          cfma_conj(h, v[g][k], t[g]);
+          yx[k] = h.x;
+          yy[k] = h.y;
+        }
       }
     }
   }
