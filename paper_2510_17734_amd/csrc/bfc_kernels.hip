@@ -278,21 +278,24 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
   for (int k = 0; k < D; ++k) acc[k] = T(0);
 #pragma unroll
   for (int k = 0; k < R; ++k) hx[k] = hy[k] = T(0);
+  // four entries per lane and step, their loads issued as one group
   for (int base = e0 + sub; base < e1; base += 16 * 4) {
-    int id[4];
+    int id[4], ent[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) id[q] = (base + 16 * q < e1) ? env_idx[base + 16 * q] : -1;
+    for (int q = 0; q < 4; ++q) {
+      ent[q] = base + 16 * q;
+      id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+    }
+    cx<T> v[4][R], t[4];
+    gather_group<T, R, 4>(env, vals, id, ent, v, t);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (id[q] < 0) continue;
-      const cx<T> t = vals[base + 16 * q];
-      cx<T> a[R];
-      load_env<T, R>(env, id[q], a);
-      herm_acc<T, R>(acc, a);
+      herm_acc<T, R>(acc, v[q]);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         cx<T> h = {hx[k], hy[k]};
-        cfma_conj(h, a[k], t);
+        cfma_conj(h, v[q][k], t[q]);
         hx[k] = h.x;
         hy[k] = h.y;
       }
@@ -327,15 +330,19 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
   }
   double r0 = 0.0, r1 = 0.0;
   for (int base = e0 + sub; base < e1; base += 16 * 4) {
-    int id[4];
+    int id[4], ent[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) id[q] = (base + 16 * q < e1) ? env_idx[base + 16 * q] : -1;
+    for (int q = 0; q < 4; ++q) {
+      ent[q] = base + 16 * q;
+      id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+    }
+    cx<T> vv[4][R], tt[4];
+    gather_group<T, R, 4>(env, vals, id, ent, vv, tt);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (id[q] < 0) continue;
-      const cx<T> t = vals[base + 16 * q];
-      cx<T> v[R];
-      load_env<T, R>(env, id[q], v);
+      const cx<T> t = tt[q];
+      const cx<T>(&v)[R] = vv[q];
       cx<T> x = {T(0), T(0)};
 #pragma unroll
       for (int k = 0; k < R; ++k) cfma(x, v[k], z[k]);
@@ -739,17 +746,26 @@ __global__ __launch_bounds__(64) void inner_ir_kernel(
 #pragma unroll
     for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
 #pragma unroll
-    for (int q = 0; q < kSubgroup; ++q) {
-      if (id[q] < 0) continue;
-      const cx<float> t = vals[e0 + q];
-      cx<float> v[R];
-      load_env<float, R>(esrc, id[q], v);
-      cx<float> x = {0.f, 0.f};
+    for (int g0 = 0; g0 < kSubgroup; g0 += kGatherGroup) {
+      if (__ballot(e0 + g0 < e1) == 0) break;
+      int gid[kGatherGroup], ent[kGatherGroup];
 #pragma unroll
-      for (int k = 0; k < R; ++k) cfma(x, m[k], v[k]);
-      const cx<float> res = {t.x - x.x, t.y - x.y};
+      for (int g = 0; g < kGatherGroup; ++g) {
+        gid[g] = id[g0 + g];
+        ent[g] = e0 + g0 + g;
+      }
+      cx<float> vv[kGatherGroup][R], tt[kGatherGroup];
+      gather_group<float, R, kGatherGroup>(esrc, vals, gid, ent, vv, tt);
 #pragma unroll
-      for (int k = 0; k < R; ++k) cfma_conj(w[k], v[k], res);  // w += conj(v) res
+      for (int g = 0; g < kGatherGroup; ++g) {
+        if (gid[g] < 0) continue;
+        cx<float> x = {0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < R; ++k) cfma(x, m[k], vv[g][k]);
+        const cx<float> res = {tt[g].x - x.x, tt[g].y - x.y};
+#pragma unroll
+        for (int k = 0; k < R; ++k) cfma_conj(w[k], vv[g][k], res);  // w += conj(v) res
+      }
     }
     // g[a*R+b] += conj(l_a) w_b (row groups) or w_a conj(rho_b) (column groups)
 #pragma unroll
@@ -1077,6 +1093,67 @@ __global__ __launch_bounds__(256) void env_level_batched(const EnvArgs<T>* tasks
   env_level_body<T, R, RIGHT>(tasks[t], b - block_off[t]);
 }
 
+// The top right levels hold few nodes, and one launch per level costs more
+// than the arithmetic.  Each of their nodes is computed here from scratch,
+// as the chain Z^(p+2)[k] ... Z^(L+1)[k] Z^(L+2)[j] (the right environment of
+// Section 5.1.1), all levels in one launch.  The products are taken in the
+// same order as level by level, so the vectors are bit-identical.  Every
+// level starts at a multiple of 64 threads, so a wavefront walks one chain
+// length, and a slice that all its nodes use is staged in LDS once.
+constexpr int kDirectLevels = 4;
+template <typename T>
+struct DirectEnvArgs {
+  const cx<T>* cores;
+  int64_t n;
+  int L, c, nlev;
+  int p[kDirectLevels];
+  int count[kDirectLevels];
+  int off[kDirectLevels + 1];  // first thread of each level, multiples of 64
+  const int32_t* node_a[kDirectLevels];
+  const int32_t* node_b[kDirectLevels];
+  cx<T>* out[kDirectLevels];
+};
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void env_right_direct_kernel(DirectEnvArgs<T> a) {
+  __shared__ cx<T> zs[4][R * R];
+  const int k = (int)(blockIdx.x * 256 + threadIdx.x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (__builtin_amdgcn_readfirstlane(k) >= a.off[a.nlev]) return;  // the whole wavefront
+  int l = 0;
+  while (l + 1 < a.nlev && k >= a.off[l + 1]) ++l;
+  l = __builtin_amdgcn_readfirstlane(l);
+  const int i = k - a.off[l];
+  const bool live = i < a.count[l];
+  const int p = a.p[l], L = a.L;
+  uint32_t u = 0, j = 0;
+  if (live) {
+    u = (uint32_t)a.node_a[l][i];
+    j = (uint32_t)a.node_b[l][i];
+  }
+  const uint32_t ib = u << p, jb = j / (uint32_t)a.c;  // the chain reads ib only as ib >> p
+  cx<T> w[R];
+  load_env<T, R>(a.cores + last_off(a.n, L, R), (int)j, w);
+  for (int m = L; m > p; --m) {
+    const cx<T>* Zc = a.cores + inner_off(a.n, L, R, m);
+    const uint32_t key = slice_key(ib, jb, L, m);
+    const uint32_t kf = __builtin_amdgcn_readfirstlane(key);
+    if (__ballot(live && key != kf) == 0) {
+      const cx<T>* src = Zc + (int64_t)kf * R * R;
+      for (int e = lane; e < R * R; e += 64) zs[wave][e] = src[e];
+      wave_sync();
+      mat_vec<T, R>(zs[wave], w);
+      wave_sync();  // every lane has read the slice before the next one lands
+    } else {
+      mat_vec<T, R>(Zc + (int64_t)key * R * R, w);
+    }
+  }
+  if (!live) return;
+  cx<T>* o = a.out[l] + (int64_t)i * R;
+#pragma unroll
+  for (int q = 0; q < R; ++q) o[q] = w[q];
+}
+
 // Residual on the observed set from the cached left environments of the last
 // core: x = l_(L+1) . Z^(L+2)[j].  Entries in the last core's order.
 template <typename T>
@@ -1225,7 +1302,35 @@ bfc_status ensure_right(Problem* P, int p, hipStream_t st) {
       break;
     }
   if (top < 0) return BFC_OK;
-  for (int q = top; q >= p; --q) {
+  // levels L-1 .. L-kDirectLevels from scratch in one launch, the rest level
+  // by level from their parents
+  int q = top;
+  {
+    DirectEnvArgs<T> d;
+    d.cores = (const cx<T>*)P->cores;
+    d.n = P->n;
+    d.L = L;
+    d.c = P->c;
+    d.nlev = 0;
+    d.off[0] = 0;
+    for (; q >= p && q >= L - kDirectLevels; --q) {
+      EnvLevel& E = P->rlev[q];
+      E.valid = true;
+      if (E.count <= 0) continue;
+      d.p[d.nlev] = q;
+      d.count[d.nlev] = E.count;
+      d.node_a[d.nlev] = E.node_a;
+      d.node_b[d.nlev] = E.node_b;
+      d.out[d.nlev] = (cx<T>*)E.vec;
+      d.off[d.nlev + 1] = d.off[d.nlev] + (E.count + 63) / 64 * 64;
+      ++d.nlev;
+    }
+    if (d.nlev > 0) {
+      env_right_direct_kernel<T, R><<<grid_for(d.off[d.nlev]), 256, 0, st>>>(d);
+      BFC_HIP_TRY(hipGetLastError());
+    }
+  }
+  for (; q >= p; --q) {
     EnvLevel& E = P->rlev[q];
     if (E.count > 0)
       env_level_kernel<T, R, 1><<<grid_for(E.count), 256, 0, st>>>(env_args<T, R>(P, q, 1));
