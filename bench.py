@@ -197,6 +197,7 @@ def cpu_baseline(w, budget_s=25.0):
 
 KIND_PATTERNS = (("inner_gram", "inner_gram_kernel"), ("inner_solve", "inner_solve_kernel"),
                  ("outer", "outer_update_kernel"), ("env", "_level_kernel"),
+                 ("env", "env_right_direct_kernel"),
                  ("residual", "residual_observed_kernel"))
 
 
@@ -259,7 +260,7 @@ def pmc_summary(fetch_dir, write_dir, copy_mib, bench_json, out, command):
               "| kernel | dispatches | FETCH KiB/dispatch | WRITE KiB/dispatch | "
               "scaled MB/launch | HBM bytes per launch | algorithmic bytes per launch | ratio |",
               "|---|---:|---:|---:|---:|---:|---:|---:|"]
-    for kind, _ in KIND_PATTERNS:
+    for kind in dict.fromkeys(k for k, _ in KIND_PATTERNS):
         f = per.get((kind, "FETCH_SIZE"))
         wv = per.get((kind, "WRITE_SIZE"))
         if not f or not wv:
@@ -306,7 +307,7 @@ def stats_summary(stats_dir, bench_json, out, command):
               "trie levels one core update needs, so only its total is comparable).", "",
               "| kind | rocprofv3 dispatches | rocprofv3 avg us | bench.py launches | bench.py avg us |",
               "|---|---:|---:|---:|---:|"]
-    for kind, _ in KIND_PATTERNS:
+    for kind in dict.fromkeys(k for k, _ in KIND_PATTERNS):
         if kind in kinds:
             c, t = kinds[kind]
             e = ev.get(kind, {})
@@ -462,7 +463,10 @@ def main():
     stats = [bfc.core_stats(prob, p) for p in range(w.L + 2)]
     cbytes = 8 if args.precision == "c64" else 16
     models = kernel_models(stats, w, cbytes, bfc.env_nodes(prob))
-    env_levels = sum(1 for q in range(w.L) if stats[q]["right_env_nodes"]) + \
+    # environment dispatches per sweep: the top four right levels share one
+    # launch, every other level has its own
+    env_levels = sum(1 for q in range(w.L - 4) if stats[q]["right_env_nodes"]) + \
+        (1 if any(stats[q]["right_env_nodes"] for q in range(max(w.L - 4, 0), w.L)) else 0) + \
         sum(1 for q in range(2, w.L + 2) if stats[q]["left_env_nodes"])
     dom = max(models, key=lambda k: kern[k][0])
     dom_ms, dom_launches = kern[dom]
