@@ -25,3 +25,9 @@ from .butterfly_als import (  # noqa: F401
     sweep,
     update_core,
 )
+from .lowrank_to_butterfly import (  # noqa: F401
+    householder_qrcp,
+    lowrank_to_butterfly,
+    side_levels,
+    sketch_shapes,
+)

@@ -1,11 +1,14 @@
 """Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
 
 This package holds no arithmetic of the completion method itself: it only
-produces operator entries, observed index sets and random starting cores.
+produces operator entries, observed index sets, random starting cores and
+the Gaussian matrices the low-rank to butterfly conversion draws.
 """
 from .generators import (  # noqa: F401
     WORKLOADS,
     batched_instances,
+    gaussian_sketches,
+    random_lowrank,
     Workload,
     green_line_entries,
     green_planes_entries,

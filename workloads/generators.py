@@ -125,6 +125,24 @@ def random_cores(n: int, L: int, r: int, seed: int, scale: float = 1.0):
     return cores
 
 
+def gaussian_sketches(n: int, L: int, r: int, p: int, seed: int):
+    """Gaussian matrices for the low-rank to butterfly conversion, entries
+    i.i.d. CN(0, 1): one (n >> l) x (r + p) matrix per row-side level
+    l = 0..ceil(L/2), then one per column-side level l = 0..floor(L/2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = [(n >> l, r + p) for l in range((L + 1) // 2 + 1)]
+    shapes += [(n >> l, r + p) for l in range(L // 2 + 1)]
+    sd = math.sqrt(0.5)
+    return [sd * (rng.standard_normal(s) + 1j * rng.standard_normal(s)) for s in shapes]
+
+
+def random_lowrank(n: int, R: int, seed: int):
+    """Factors A, B (n x R, entries CN(0, 1/R)) of X = A B^T."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sd = math.sqrt(0.5 / R)
+    return [sd * (rng.standard_normal((n, R)) + 1j * rng.standard_normal((n, R))) for _ in range(2)]
+
+
 @dataclass
 class Workload:
     """One completion instance: sizes, observed entries, test entries, start."""
