@@ -286,6 +286,37 @@ bfc_status bfc_autotune_item_size(bfc_problem* const* problems, int32_t count, i
                                   const int32_t* candidates, int32_t ncand, int32_t* chosen,
                                   double* ms_per_sweep, void* hip_stream);
 
+/*
+ * Initial guess of Sec. 5.2: low-rank completion is a problem with L = 0
+ * (x_ij = Z^1[i] . Z^2[j], rank R), run with the calls above; this call turns
+ * its result X = A B^T into butterfly cores by Alg.
+ * "Randomized_LR_to_Butterfly": per row leaf block the first r columns of a
+ * column-pivoted QR of the Gaussian sketch A_block (B^T O_0); per inner level
+ * the two child blocks' projected factors stacked (2r x R), sketched with
+ * B restricted to the current column block, the pivoted QR's first r
+ * columns giving the two children's r x r slices; the same from the column
+ * side; the middle core (core ceil(L/2)) absorbs V W^T.  Rows take
+ * ceil(L/2) inner levels, columns floor(L/2).  Exact (up to rounding) when
+ * R <= r.
+ *
+ * d_A, d_B: device, n x R complex128 (interleaved re/im), row-major, caller
+ *   owned; A = Z^1 and B = Z^2 of the L = 0 problem (bfc_get_cores layout).
+ * d_sketches: device complex128, the Gaussian matrices the algorithm draws,
+ *   concatenated row-major: row-side levels l = 0..ceil(L/2), each
+ *   (n >> l) x (r + p), then column-side levels l = 0..floor(L/2), same
+ *   shapes.  The caller draws them (any distribution the caller chooses;
+ *   the algorithm calls for Gaussian).
+ * d_cores_out: device complex128, bfc_num_params(n, L, r) values in the
+ *   bfc_get_cores layout; pass it to bfc_init_cores or bfc_set_cores.
+ * Requires L >= 1, n = c 2^L with r <= c <= 64, 1 <= r <= 8, 1 <= R <= 16,
+ * p >= 0, r + p <= 32; else BFC_EINVAL.  Allocates a scratch buffer of
+ * 2^L (4 r R + R (r + p)) complex values for the call and synchronizes
+ * hip_stream before returning.
+ */
+bfc_status bfc_lowrank_to_butterfly(int64_t n, int32_t L, int32_t r, int32_t R, int32_t p,
+                                    const void* d_A, const void* d_B, const void* d_sketches,
+                                    void* d_cores_out, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,4 +36,5 @@ from .api import (  # noqa: F401
     use_graphs,
     set_item_size,
     autotune_item_size,
+    lowrank_to_butterfly,
 )

@@ -54,6 +54,7 @@ EXPORTS = (
     "bfc_batch_destroy",
     "bfc_set_item_size",
     "bfc_autotune_item_size",
+    "bfc_lowrank_to_butterfly",
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
@@ -135,6 +136,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                            ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
                                            vp]
     lib.bfc_autotune_item_size.restype = i32
+    lib.bfc_lowrank_to_butterfly.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.bfc_lowrank_to_butterfly.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

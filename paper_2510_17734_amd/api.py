@@ -326,3 +326,32 @@ def autotune_item_size(problems, sweeps: int = 2, candidates=(64, 128, 256, 512)
                                               len(candidates), ctypes.byref(chosen), ms,
                                               _stream(stream)), "bfc_autotune_item_size")
     return int(chosen.value), {c: float(ms[k]) for k, c in enumerate(candidates)}
+
+
+def lowrank_to_butterfly(A, B, L: int, r: int, p: int, sketches, *, device="cuda:0",
+                         stream=None) -> torch.Tensor:
+    """bfc_lowrank_to_butterfly: butterfly cores (ABI layout, complex128 on the
+    device) from the factors A, B (n x R) of X = A B^T.  ``sketches`` are the
+    Gaussian matrices the algorithm draws (row-side levels, then column-side
+    levels), as arrays or tensors, or one flat complex128 tensor."""
+    device = torch.device(device)
+    A_t = _dev_c128(A, device)
+    B_t = _dev_c128(B, device)
+    if A_t.dim() != 2 or A_t.shape != B_t.shape:
+        raise ValueError("A and B must be n x R of the same shape")
+    n, R = int(A_t.shape[0]), int(A_t.shape[1])
+    if isinstance(sketches, (list, tuple)):
+        sk = torch.cat([_dev_c128(s, device).reshape(-1) for s in sketches])
+    else:
+        sk = _dev_c128(sketches, device).reshape(-1)
+    lr, lc = (L + 1) // 2, L // 2
+    need = sum((n >> l) * (r + p) for l in range(lr + 1)) + \
+        sum((n >> l) * (r + p) for l in range(lc + 1))
+    if L >= 1 and sk.numel() != need:
+        raise ValueError(f"expected {need} sketch values, got {sk.numel()}")
+    lib = _lib.load()
+    out = torch.empty(int(lib.bfc_num_params(n, L, r)), dtype=torch.complex128, device=device)
+    _check(lib.bfc_lowrank_to_butterfly(n, int(L), int(r), R, int(p), _ptr(A_t), _ptr(B_t),
+                                        _ptr(sk), _ptr(out), _stream(stream)),
+           "bfc_lowrank_to_butterfly")
+    return out
