@@ -14,6 +14,11 @@ Besides the JSON fields of the bench contract the line carries:
   fp64          the same sweep run in complex128 / FP64 on the GPU
   convergence   train / test error per sweep from the random start and the
                 time to a test error of 1e-3 (or the floor reached)
+  bf16gram      the same sweep with the BF16-input Gram and refinement
+  batching      the 64-instance workload swept in shared launches
+  warm_start    Sec. 5.2's initial guess (low-rank completion, then the
+                randomized low-rank to butterfly conversion) against the
+                random start, on the 256-point workload and on this one
 """
 from __future__ import annotations
 
@@ -389,6 +394,8 @@ def main():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the low-rank initial guess record")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -601,6 +608,75 @@ def main():
                 f"at_{c['sweeps_run']}_sweeps": c["final_test_err"],
                 "sweeps_to_1e-3": c["sweeps"], "time_to_1e-3_s": c["time_s"]}
             for m, c in modes.items()}
+
+    def warm_start(wl, prec, lr_sweeps, cap, p=4):
+        """Sec. 5.2's initial guess against the random start on workload wl:
+        low-rank completion (L = 0, rank r, lr_sweeps sweeps from random
+        factors), bfc_lowrank_to_butterfly (oversampling p), then butterfly
+        sweeps up to cap.  The clock covers all three stages and the per-sweep
+        residuals (not the layout builds of the two problems); the test error
+        is reported after 20 butterfly sweeps (the paper's t_max), at its
+        floor, and the time to 1e-3 if reached."""
+        from workloads import gaussian_sketches, random_cores
+
+        rms = float(np.sqrt(np.mean(np.abs(wl.vals) ** 2)))
+        tr = (torch.as_tensor(wl.test_rows), torch.as_tensor(wl.test_cols),
+              torch.as_tensor(wl.test_vals))
+
+        def sweeps(flat, t_before):
+            prob_b = bfc.init_cores(bfc.Config(n=wl.n, L=wl.L, r=wl.r, precision=prec,
+                                               reg_rel=1e-10),
+                                    wl.rows, wl.cols, wl.vals, flat, device=dev)
+            hist, hit = [], None
+            e0 = bfc.relative_error(prob_b, *tr)
+            torch.cuda.synchronize()
+            t_start = time.perf_counter() - t_before
+            for s in range(cap):
+                bfc.sweep(prob_b)
+                te = bfc.relative_error(prob_b, *tr)
+                hist.append(te)
+                if hit is None and te <= 1e-3:
+                    hit = (s + 1, time.perf_counter() - t_start)
+                    break
+            prob_b.close()
+            return {"start_test_err": e0, "test_err_at_20_sweeps": hist[min(20, len(hist)) - 1],
+                    "floor_test_err": min(hist), "sweeps_run": len(hist),
+                    "sweeps_to_1e-3": hit[0] if hit else None,
+                    "time_to_1e-3_s": round(hit[1], 5) if hit else None}
+
+        rand = sweeps(bfc.flatten_cores(wl.cores0), 0.0)
+        lr0 = random_cores(wl.n, 0, wl.r, wl.seed + 1, scale=rms * np.sqrt(wl.r))
+        lr = bfc.init_cores(bfc.Config(n=wl.n, L=0, r=wl.r, precision=prec, reg_rel=1e-6),
+                            wl.rows, wl.cols, wl.vals, lr0, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(lr_sweeps):
+            bfc.sweep(lr)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        lr_test = bfc.relative_error(lr, *tr)
+        ab = bfc.get_cores(lr).reshape(2, wl.n, wl.r)
+        lr.close()
+        sk = gaussian_sketches(wl.n, wl.L, wl.r, p, seed=wl.seed + 2)
+        bfc.lowrank_to_butterfly(ab[0], ab[1], wl.L, wl.r, p, sk, device=dev)  # module load
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        flat = bfc.lowrank_to_butterfly(ab[0], ab[1], wl.L, wl.r, p, sk, device=dev)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        warm = sweeps(flat, (t2 - t1) + (t4 - t3))
+        return {"workload": wl.name, "precision": prec, "lowrank_sweeps": lr_sweeps,
+                "lowrank_rank": wl.r, "oversampling": p,
+                "lowrank_test_err": lr_test, "lowrank_ms": round(1e3 * (t2 - t1), 3),
+                "conversion_ms": round(1e3 * (t4 - t3), 3),
+                "conversion_ms_note": "second call, host-to-device copy of the sketches included",
+                "warm": warm, "random": rand}
+
+    if not args.no_warm:
+        out["warm_start"] = [
+            warm_start(make_workload("green-line-256"), "c128", 3, 20),
+            warm_start(w, args.precision, 3, args.sweeps_to_target),
+        ]
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
