@@ -37,6 +37,7 @@ PEAKS = {  # MI355X published dense peaks
     "hbm_GBs": 8000.0,
     "fp32_TFs": 157.3,
     "fp64_TFs": 78.6,
+    "fp32_matrix_TFs": 157.3,
 }
 
 
@@ -282,6 +283,76 @@ def pmc_summary(fetch_dir, write_dir, copy_mib, bench_json, out, command):
     print("\n".join(lines))
 
 
+MFMA_COUNTERS = ("MfmaUtil", "MfmaFlopsF32", "VALUBusy", "VALUUtilization")
+
+
+def mfma_summary(pmc_dir, bench_json, out, command):
+    """Per-kernel matrix-core and vector-ALU activity from one rocprofv3
+    --pmc run of the derived counters MFMA_COUNTERS (per dispatch: MFMA busy
+    share of SIMD cycles, FP32 MFMA flops, VALU busy share, active-lane share),
+    written as a markdown summary that bench.py reads back."""
+    import csv
+
+    per = {}
+    with open(find_file(pmc_dir, "counter_collection.csv")) as fh:
+        for row in csv.DictReader(fh):
+            kind = kernel_kind(row["Kernel_Name"])
+            if kind and row["Counter_Name"] in MFMA_COUNTERS:
+                per.setdefault((kind, row["Counter_Name"]), []).append(float(row["Counter_Value"]))
+    rec = {}
+    if bench_json:
+        with open(bench_json) as fh:
+            for ln in fh:
+                if ln.startswith("{"):
+                    rec = json.loads(ln)
+    title = "# Matrix-core and VALU activity per kernel launch"
+    if rec:
+        title += f": {rec['config']['workload']}, {rec['config']['precision']}"
+    lines = [title, "", "One `rocprofv3 --pmc` run of the derived counters "
+             + ", ".join(f"`{c}`" for c in MFMA_COUNTERS) + " (rocprofv3's definitions: "
+             "MfmaUtil = 100 SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs), "
+             "MfmaFlopsF32 = 512 SQ_INSTS_VALU_MFMA_MOPS_F32, VALUBusy = 100 "
+             "SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE, VALUUtilization = active lanes "
+             "per VALU instruction):", "", "```"] + command + ["```", "",
+             f"source_sha256: {source_digest()}", "",
+             "| kernel | dispatches | MfmaUtil % | MFMA FP32 flops per launch | VALUBusy % | "
+             "VALUUtilization % |", "|---|---:|---:|---:|---:|---:|"]
+    for kind in dict.fromkeys(k for k, _ in KIND_PATTERNS):
+        vals = {c: per.get((kind, c)) for c in MFMA_COUNTERS}
+        if not vals["MfmaUtil"]:
+            continue
+        avg = {c: (sum(v) / len(v) if v else float("nan")) for c, v in vals.items()}
+        lines.append(f"| `{kind}` | {len(vals['MfmaUtil'])} | {avg['MfmaUtil']:.2f} | "
+                     f"{avg['MfmaFlopsF32']:.0f} | {avg['VALUBusy']:.2f} | "
+                     f"{avg['VALUUtilization']:.2f} |")
+    lines.append("")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def stored_mfma(workload, precision, kernel):
+    """(MfmaUtil %, FP32 MFMA flops per launch) of `kernel` from the committed
+    summary of this workload, or None when absent or the sources changed."""
+    path = os.path.join(ROOT, "profiles", f"mfma_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    digest, table = None, {}
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("source_sha256:"):
+                digest = ln.split(":", 1)[1].strip()
+            cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+            if len(cells) >= 4 and cells[0].startswith("`") and cells[0] != "`kernel`":
+                try:
+                    table[cells[0].strip("`")] = (float(cells[2]), float(cells[3]))
+                except ValueError:
+                    pass
+    if digest != source_digest():
+        return None
+    return table.get(kernel)
+
+
 def stats_summary(stats_dir, bench_json, out, command):
     """Markdown summary of rocprofv3 --kernel-trace --stats (kernel_stats.csv),
     with bench.py's own per-kernel event averages of the same run beside it."""
@@ -400,6 +471,9 @@ def main():
                     help="run one device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarize two rocprofv3 --pmc runs instead of benchmarking")
+    ap.add_argument("--mfma-summary", metavar="PMC_DIR",
+                    help="summarize a rocprofv3 --pmc run of the MFMA/VALU counters instead of "
+                         "benchmarking")
     ap.add_argument("--stats-summary", metavar="STATS_DIR",
                     help="summarize a rocprofv3 --kernel-trace --stats run instead of benchmarking")
     ap.add_argument("--bench-json", help="bench output of the profiled run (for the summaries)")
@@ -413,6 +487,9 @@ def main():
         return
     if args.stats_summary:
         stats_summary(args.stats_summary, args.bench_json, args.out, args.command)
+        return
+    if args.mfma_summary:
+        mfma_summary(args.mfma_summary, args.bench_json, args.out, args.command)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -502,6 +579,17 @@ def main():
         "avg_launch_us": round(1e3 * dom_ms / max(dom_launches, 1), 3),
         "launches": dom_launches,
     }
+    # matrix-core activity of the same kernel from the committed counter
+    # summary: busy share of SIMD cycles and the FP32 MFMA rate it implies at
+    # this run's launch duration, against the FP32 matrix peak
+    mf = stored_mfma(w.name, args.precision, dom)
+    if mf is not None:
+        rate = mf[1] / secs_dom / 1e12
+        roofline["mfma"] = {"util_pct": mf[0], "flops_per_launch": mf[1],
+                            "achieved_TFs": round(rate, 3), "peak_TFs": PEAKS["fp32_matrix_TFs"],
+                            "frac": round(rate / PEAKS["fp32_matrix_TFs"], 5)}
+    else:
+        roofline["mfma"] = None
     kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / max(v[1], 1), 3)} for k, v in kern.items()}
     train_err = math.sqrt(last[0] / last[1])
