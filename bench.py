@@ -584,7 +584,7 @@ def main():
     # this run's launch duration, against the FP32 matrix peak
     mf = stored_mfma(w.name, args.precision, dom)
     if mf is not None:
-        rate = mf[1] / secs_dom / 1e12
+        rate = mf[1] / (dom_ms * 1e-3 / max(dom_launches, 1)) / 1e12  # per launch
         roofline["mfma"] = {"util_pct": mf[0], "flops_per_launch": mf[1],
                             "achieved_TFs": round(rate, 3), "peak_TFs": PEAKS["fp32_matrix_TFs"],
                             "frac": round(rate / PEAKS["fp32_matrix_TFs"], 5)}
@@ -759,6 +759,9 @@ def main():
                 "conversion_ms": round(1e3 * (t4 - t3), 3),
                 "conversion_ms_note": "second call, host-to-device copy of the sketches included",
                 "warm": warm, "random": rand}
+
+    if not args.no_batch:
+        out["batching"] = batched_record(bfc, torch, dev, max(3, args.steps // 2))
 
     if not args.no_warm:
         out["warm_start"] = [
