@@ -31,3 +31,4 @@ from .lowrank_to_butterfly import (  # noqa: F401
     side_levels,
     sketch_shapes,
 )
+from .adam import adam_state, adam_sweep, adam_update, gradient  # noqa: F401
