@@ -287,6 +287,26 @@ bfc_status bfc_autotune_item_size(bfc_problem* const* problems, int32_t count, i
                                   double* ms_per_sweep, void* hip_stream);
 
 /*
+ * One iteration t (1-based) of Alg. "ADAM for Butterfly Completion"
+ * (Sec. 5.1.2): cores 0..L+1 in order, each moved by one Alg. "ADAM_Update"
+ * step on the gradient of phi = 1/2 ||P(X - T)||^2 at the current cores
+ * (the core before it already moved), from the same environments as the ALS
+ * update (eq. (grad_butterfly_1), (grad_butterfly_l), (grad_butterfly_last)).
+ * For complex data the gradient is sum_e conj(a_e)(x_e - t_e) and the second
+ * moment accumulates |g|^2: m <- beta1 m + (1 - beta1) g,
+ * v <- beta2 v + (1 - beta2) |g|^2, s <- s - alpha m_hat / (sqrt(v_hat) + sigma)
+ * with m_hat = m / (1 - beta1^t), v_hat = v / (1 - beta2^t).  Gradients are
+ * accumulated in the compute precision (FP32 in the complex64 modes), the
+ * step in FP64.  The moments live in the problem (zero at the first call;
+ * bfc_adam_reset zeroes them for a new run); the caller passes t.
+ * Asynchronous on hip_stream.  BFC_EINVAL unless t >= 1, alpha > 0,
+ * 0 <= beta1, beta2 < 1, sigma >= 0.
+ */
+bfc_status bfc_adam_sweep(bfc_problem* p, int32_t t, double alpha, double beta1, double beta2,
+                          double sigma, void* hip_stream);
+bfc_status bfc_adam_reset(bfc_problem* p, void* hip_stream);
+
+/*
  * Initial guess of Sec. 5.2: low-rank completion is a problem with L = 0
  * (x_ij = Z^1[i] . Z^2[j], rank R), run with the calls above; this call turns
  * its result X = A B^T into butterfly cores by Alg.

@@ -37,4 +37,6 @@ from .api import (  # noqa: F401
     set_item_size,
     autotune_item_size,
     lowrank_to_butterfly,
+    adam_sweep,
+    adam_reset,
 )

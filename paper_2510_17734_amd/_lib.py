@@ -55,6 +55,8 @@ EXPORTS = (
     "bfc_set_item_size",
     "bfc_autotune_item_size",
     "bfc_lowrank_to_butterfly",
+    "bfc_adam_sweep",
+    "bfc_adam_reset",
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
@@ -138,6 +140,11 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_autotune_item_size.restype = i32
     lib.bfc_lowrank_to_butterfly.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.bfc_lowrank_to_butterfly.restype = i32
+    d = ctypes.c_double
+    lib.bfc_adam_sweep.argtypes = [P, i32, d, d, d, d, vp]
+    lib.bfc_adam_sweep.restype = i32
+    lib.bfc_adam_reset.argtypes = [P, vp]
+    lib.bfc_adam_reset.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

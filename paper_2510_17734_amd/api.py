@@ -355,3 +355,15 @@ def lowrank_to_butterfly(A, B, L: int, r: int, p: int, sketches, *, device="cuda
                                         _ptr(sk), _ptr(out), _stream(stream)),
            "bfc_lowrank_to_butterfly")
     return out
+
+
+def adam_sweep(p: Problem, t: int, alpha: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+               sigma: float = 1e-8, stream=None):
+    """bfc_adam_sweep: iteration t (1-based) of ADAM butterfly completion."""
+    _check(_lib.load().bfc_adam_sweep(p.handle, int(t), float(alpha), float(beta1), float(beta2),
+                                      float(sigma), _stream(stream)), "bfc_adam_sweep")
+
+
+def adam_reset(p: Problem, stream=None):
+    """bfc_adam_reset: zero the ADAM moments (a new run starts at t = 1)."""
+    _check(_lib.load().bfc_adam_reset(p.handle, _stream(stream)), "bfc_adam_reset")

@@ -268,6 +268,50 @@ bfc_status bfc_sweep(bfc_problem* p, void* hip_stream) {
   return BFC_OK;
 }
 
+bfc_status bfc_adam_sweep(bfc_problem* p, int32_t t, double alpha, double beta1, double beta2,
+                          double sigma, void* hip_stream) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  if (t < 1 || !(alpha > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) ||
+      !(beta2 >= 0.0 && beta2 < 1.0) || !(sigma >= 0.0)) {
+    set_error("bfc_adam_sweep: need t >= 1, alpha > 0, 0 <= beta1, beta2 < 1, sigma >= 0");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t real = p->elem / 2;
+  if (!p->adam_m) {
+    BFC_TRY(dev_alloc(p, &p->adam_m, (size_t)p->nparams * p->elem));
+    BFC_TRY(dev_alloc(p, &p->adam_v, (size_t)p->nparams * real));
+    BFC_HIP_TRY(hipMemsetAsync(p->adam_m, 0, (size_t)p->nparams * p->elem, st));
+    BFC_HIP_TRY(hipMemsetAsync(p->adam_v, 0, (size_t)p->nparams * real, st));
+  }
+  if (p->L >= 1 && p->adam_part_items < p->max_items) {
+    if (p->adam_part) BFC_TRY(dev_free(p, p->adam_part));
+    p->adam_part = nullptr;
+    BFC_TRY(dev_alloc(p, &p->adam_part,
+                      (size_t)std::max(p->max_items, 1) * 2 * p->r * p->r * real));
+    p->adam_part_items = std::max(p->max_items, 1);
+  }
+  for (int core = 0; core <= p->L + 1; ++core)
+    BFC_TRY(launch_adam_core(p, core, t, alpha, beta1, beta2, sigma, st));
+  return BFC_OK;
+}
+
+bfc_status bfc_adam_reset(bfc_problem* p, void* hip_stream) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (p->adam_m) {
+    BFC_HIP_TRY(hipMemsetAsync(p->adam_m, 0, (size_t)p->nparams * p->elem, st));
+    BFC_HIP_TRY(hipMemsetAsync(p->adam_v, 0, (size_t)p->nparams * (p->elem / 2), st));
+  }
+  return BFC_OK;
+}
+
 bfc_status bfc_use_graphs(bfc_problem* p, int32_t enable) {
   if (!p) {
     set_error("null problem");

@@ -159,6 +159,13 @@ struct Problem {
   double* ir_lam = nullptr;
   void* ir_old = nullptr;
   double* red = nullptr;             // residual reduction scratch
+  // ADAM (bfc_adam_sweep): first moments (complex), second moments (real),
+  // both in the cores' layout, and per-item residual vectors; allocated at
+  // the first ADAM call
+  void* adam_m = nullptr;
+  void* adam_v = nullptr;
+  void* adam_part = nullptr;
+  int32_t adam_part_items = 0;
   double* fused_res = nullptr;       // 2 per fiber of the last core: residual norms
   bool fused_res_valid = false;      // fused_res belongs to the current cores
   size_t red_len = 0;
@@ -220,6 +227,8 @@ inline int64_t num_params(int64_t n, int L, int r) {
 bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols,
                         const void* d_vals, hipStream_t st);
 bfc_status launch_sweep_core(Problem* P, int core, hipStream_t st);
+bfc_status launch_adam_core(Problem* P, int core, int t, double alpha, double beta1,
+                            double beta2, double sigma, hipStream_t st);
 bfc_status build_items(Problem* P, int core, hipStream_t st);
 bfc_status dev_free(Problem* P, void* ptr);
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,

@@ -18,6 +18,7 @@
 // Work items (runs of subgroups of one slice) write partial products; a
 // second kernel sums them per slice in a fixed order, forms the Hermitian
 // system in FP64 and solves it with one wavefront.
+#include <cmath>
 #include <type_traits>
 
 #include "bfc_device.h"
@@ -692,43 +693,45 @@ __global__ __launch_bounds__(64) void inner_gram_bf16_kernel(
       }
 }
 
-// Refinement residual of the BF16-Gram solves, recomputed from the entries in
-// FP32: per work item, g = sum_e conj(a_e) (t_e - a_e . s0) over its
+// Residual vector of an inner core's slices at their current values,
+// recomputed from the entries in the compute precision T (FP32 for the
+// refinement of the BF16-Gram solves, T for the ADAM gradients, which are its
+// negation): per work item, g = sum_e conj(a_e) (t_e - a_e . s0) over its
 // subgroups, with s0 the slice just solved for (a_e = l (x) rho, so a_e . s0 =
 // l^T S0 rho).  Row groups share l: v = l^T S0 once, then per entry
 // res = t - v . rho and w += conj(rho) res, and g += conj(l) (x) w.  Column
 // groups share rho: u = S0 rho, res = t - l . u, w += conj(l) res,
 // g += w (x) conj(rho).  Output: ir_part[item][2 d] (re, im interleaved),
 // the wavefront's lanes summed in a fixed order.
-template <int R, int BYROW>
+template <typename T, int R, int BYROW>
 __global__ __launch_bounds__(64) void inner_ir_kernel(
-    const cx<float>* lenv, const int32_t* lidx, const cx<float>* renv, const int32_t* ridx,
-    const cx<float>* vals, const int32_t* sub_off, const WorkItem* items, const cx<float>* slices,
-    float* ir_part) {
+    const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv, const int32_t* ridx,
+    const cx<T>* vals, const int32_t* sub_off, const WorkItem* items, const cx<T>* slices,
+    T* ir_part) {
   constexpr int D = R * R, LDR = 2 * D + 1;
-  __shared__ float red[64 * LDR];
-  __shared__ cx<float> S0[D];
+  __shared__ T red[64 * LDR];
+  __shared__ cx<T> S0[D];
   const int lane = threadIdx.x;
   const int item = xcd_swizzle(blockIdx.x, gridDim.x);
   const WorkItem it = items[item];
   for (int k = lane; k < D; k += 64) S0[k] = slices[(int64_t)it.tile * D + k];
   __syncthreads();
-  float gx[D], gy[D];
+  T gx[D], gy[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) gx[k] = gy[k] = 0.f;
+  for (int k = 0; k < D; ++k) gx[k] = gy[k] = T(0);
   for (int base = it.sub0; base < it.sub1; base += 64) {
     const int s = base + lane;
     if (s >= it.sub1) continue;
     const int e0 = sub_off[s], e1 = sub_off[s + 1];
-    cx<float> sh[R], m[R], w[R];
+    cx<T> sh[R], m[R], w[R];
     if (BYROW)
-      load_env<float, R>(lenv, lidx[e0], sh);
+      load_env<T, R>(lenv, lidx[e0], sh);
     else
-      load_env<float, R>(renv, ridx[e0], sh);
+      load_env<T, R>(renv, ridx[e0], sh);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      m[k] = cx<float>{0.f, 0.f};
-      w[k] = cx<float>{0.f, 0.f};
+      m[k] = cx<T>{T(0), T(0)};
+      w[k] = cx<T>{T(0), T(0)};
     }
     // BYROW: m_b = sum_a l_a S0[a][b]; else m_a = sum_b S0[a][b] rho_b
 #pragma unroll
@@ -741,7 +744,7 @@ __global__ __launch_bounds__(64) void inner_ir_kernel(
           cfma(m[a], S0[a * R + b], sh[b]);
       }
     const int32_t* eidx = BYROW ? ridx : lidx;
-    const cx<float>* esrc = BYROW ? renv : lenv;
+    const cx<T>* esrc = BYROW ? renv : lenv;
     int id[kSubgroup];
 #pragma unroll
     for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
@@ -754,15 +757,15 @@ __global__ __launch_bounds__(64) void inner_ir_kernel(
         gid[g] = id[g0 + g];
         ent[g] = e0 + g0 + g;
       }
-      cx<float> vv[kGatherGroup][R], tt[kGatherGroup];
-      gather_group<float, R, kGatherGroup>(esrc, vals, gid, ent, vv, tt);
+      cx<T> vv[kGatherGroup][R], tt[kGatherGroup];
+      gather_group<T, R, kGatherGroup>(esrc, vals, gid, ent, vv, tt);
 #pragma unroll
       for (int g = 0; g < kGatherGroup; ++g) {
         if (gid[g] < 0) continue;
-        cx<float> x = {0.f, 0.f};
+        cx<T> x = {T(0), T(0)};
 #pragma unroll
         for (int k = 0; k < R; ++k) cfma(x, m[k], vv[g][k]);
-        const cx<float> res = {tt[g].x - x.x, tt[g].y - x.y};
+        const cx<T> res = {tt[g].x - x.x, tt[g].y - x.y};
 #pragma unroll
         for (int k = 0; k < R; ++k) cfma_conj(w[k], vv[g][k], res);  // w += conj(v) res
       }
@@ -772,8 +775,8 @@ __global__ __launch_bounds__(64) void inner_ir_kernel(
     for (int a = 0; a < R; ++a)
 #pragma unroll
       for (int b = 0; b < R; ++b) {
-        const cx<float> p = BYROW ? sh[a] : sh[b];
-        const cx<float> q = BYROW ? w[b] : w[a];
+        const cx<T> p = BYROW ? sh[a] : sh[b];
+        const cx<T> q = BYROW ? w[b] : w[a];
         gx[a * R + b] += p.x * q.x + p.y * q.y;  // conj(p) q
         gy[a * R + b] += p.x * q.y - p.y * q.x;
       }
@@ -785,7 +788,7 @@ __global__ __launch_bounds__(64) void inner_ir_kernel(
   }
   __syncthreads();
   for (int k = lane; k < 2 * D; k += 64) {
-    float acc = 0.f;
+    T acc = T(0);
     for (int l = 0; l < 64; ++l) acc += red[l * LDR + k];
     ir_part[(int64_t)item * 2 * D + k] = acc;
   }
@@ -1437,11 +1440,11 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
         {
           ProfScope ps(&P->prof, KIND_INNER_IR, st);
           if (C.group_by_row)
-            inner_ir_kernel<R, 1><<<C.nitems, 64, 0, st>>>(
+            inner_ir_kernel<float, R, 1><<<C.nitems, 64, 0, st>>>(
                 lenv, lidx, renv, ridx, (const cx<float>*)C.vals, C.sub_off, C.items, slices,
                 (float*)P->ir_part);
           else
-            inner_ir_kernel<R, 0><<<C.nitems, 64, 0, st>>>(
+            inner_ir_kernel<float, R, 0><<<C.nitems, 64, 0, st>>>(
                 lenv, lidx, renv, ridx, (const cx<float>*)C.vals, C.sub_off, C.items, slices,
                 (float*)P->ir_part);
         }
@@ -1458,6 +1461,179 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   }
   P->fused_res_valid = (p == L + 1);
   // core p changed: right levels below it and left levels above it are stale
+  for (int q = 0; q < p && q < L; ++q) P->rlev[q].valid = false;
+  for (int q = p + 1; q <= L + 1; ++q)
+    if (q >= 2) P->llev[q].valid = false;
+  return BFC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ADAM for butterfly completion (Sec. 5.1.2, Alg. "ADAM for Butterfly
+// Completion" and Alg. "ADAM_Update"): per core, the gradient
+// g = sum_e conj(a_e) (x_e - t_e) of phi at the current cores (the Wirtinger
+// gradient; the printed (x - t) v is its real-data form) from the same
+// environments as the ALS update, then one ADAM step on every parameter of
+// the core: m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) |g|^2,
+// s <- s - alpha m_hat / (sqrt(v_hat) + sigma).  The step itself is FP64.
+// ---------------------------------------------------------------------------
+struct AdamArgs {
+  double alpha, b1, b2, sigma;
+  double c1, c2;  // 1 - b1^t, 1 - b2^t
+};
+
+template <typename T>
+__device__ inline void adam_step(cx<T>& s, cx<T>& m, T& v, double gx, double gy,
+                                 const AdamArgs& a) {
+  const double mx = a.b1 * (double)m.x + (1.0 - a.b1) * gx;
+  const double my = a.b1 * (double)m.y + (1.0 - a.b1) * gy;
+  const double vv = a.b2 * (double)v + (1.0 - a.b2) * (gx * gx + gy * gy);
+  const double den = sqrt(vv / a.c2) + a.sigma;
+  const double step = a.alpha / (a.c1 * den);
+  s = cx<T>{T((double)s.x - step * mx), T((double)s.y - step * my)};
+  m = cx<T>{T(mx), T(my)};
+  v = T(vv);
+}
+
+// Outer core: 16 lanes per fiber sum conj(a_e) (x_e - t_e) over the fiber's
+// entries (x_e = z . a_e with z the fiber's current value), reduce over the
+// row of 16 lanes, and lane k < R steps element k.
+template <typename T, int R>
+__global__ __launch_bounds__(kOuterThreads) void outer_adam_kernel(
+    cx<T>* fibers, const cx<T>* env, const int32_t* env_idx, const cx<T>* vals,
+    const int32_t* blk_off, int nblocks, cx<T>* mom, T* vel, AdamArgs a) {
+  const int sub = threadIdx.x & 15;
+  const int b = (int)((blockIdx.x * kOuterThreads + threadIdx.x) >> 4);
+  int e0 = 0, e1 = 0;
+  if (b < nblocks) {
+    e0 = blk_off[b];
+    e1 = blk_off[b + 1];
+  }
+  cx<T> z[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    z[k] = b < nblocks ? fibers[(int64_t)b * R + k] : cx<T>{T(0), T(0)};
+  T gx[R], gy[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) gx[k] = gy[k] = T(0);
+  for (int base = e0 + sub; base < e1; base += 16 * 4) {
+    int id[4], ent[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ent[q] = base + 16 * q;
+      id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+    }
+    cx<T> v[4][R], t[4];
+    gather_group<T, R, 4>(env, vals, id, ent, v, t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (id[q] < 0) continue;
+      cx<T> x = {T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < R; ++k) cfma(x, z[k], v[q][k]);
+      const cx<T> res = {x.x - t[q].x, x.y - t[q].y};
+#pragma unroll
+      for (int k = 0; k < R; ++k) {  // g += conj(a) res
+        cx<T> h = {gx[k], gy[k]};
+        cfma_conj(h, v[q][k], res);
+        gx[k] = h.x;
+        gy[k] = h.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    gx[k] = row16_sum(gx[k]);
+    gy[k] = row16_sum(gy[k]);
+  }
+  if (b >= nblocks || sub >= R) return;
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (k == sub) {
+      sx = (double)gx[k];
+      sy = (double)gy[k];
+    }
+  const int64_t o = (int64_t)b * R + sub;
+  cx<T> sv = fibers[o], mv = mom[o];
+  T vv = vel[o];
+  adam_step(sv, mv, vv, sx, sy, a);
+  fibers[o] = sv;
+  mom[o] = mv;
+  vel[o] = vv;
+}
+
+// Inner core: the slice's work items' residual vectors (sum conj(a)(t - x),
+// the negated gradient) summed in a fixed order, then one ADAM step per
+// element (thread k of the slice's wavefront).
+template <typename T, int R>
+__global__ __launch_bounds__(64) void inner_adam_kernel(cx<T>* slices, const T* part,
+                                                        const int32_t* tile_items, cx<T>* mom,
+                                                        T* vel, AdamArgs a) {
+  constexpr int D = R * R;
+  const int tile = blockIdx.x, k = threadIdx.x;
+  if (k >= D) return;
+  const int it0 = tile_items[tile], it1 = tile_items[tile + 1];
+  double gx = 0.0, gy = 0.0;
+  for (int it = it0; it < it1; ++it) {
+    gx -= (double)part[(int64_t)it * 2 * D + 2 * k];
+    gy -= (double)part[(int64_t)it * 2 * D + 2 * k + 1];
+  }
+  const int64_t o = (int64_t)tile * D + k;
+  cx<T> sv = slices[o], mv = mom[o];
+  T vv = vel[o];
+  adam_step(sv, mv, vv, gx, gy, a);
+  slices[o] = sv;
+  mom[o] = mv;
+  vel[o] = vv;
+}
+
+template <typename T, int R>
+bfc_status adam_core_t(Problem* P, int p, const AdamArgs& a, hipStream_t st) {
+  cx<T>* cores = (cx<T>*)P->cores;
+  const CoreLayout& C = P->lay[p];
+  const int L = P->L;
+  {
+    ProfScope ps(&P->prof, KIND_ENV, st);
+    BFC_TRY(ensure_right<T, R>(P, p, st));
+    BFC_TRY(ensure_left<T, R>(P, p, st));
+  }
+  const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R)
+                               : (p <= L - 1 ? (const cx<T>*)P->rlev[p].vec : nullptr);
+  const int32_t* ridx = (p == L) ? C.cols : C.rnode;
+  const cx<T>* lenv = (p == 1) ? cores : (p >= 2 ? (const cx<T>*)P->llev[p].vec : nullptr);
+  const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
+  const int64_t off = p == 0 ? 0 : (p == L + 1 ? last_off(P->n, L, R) : inner_off(P->n, L, R, p));
+  cx<T>* mom = (cx<T>*)P->adam_m + off;
+  T* vel = (T*)P->adam_v + off;
+  if (p == 0 || p == L + 1) {
+    cx<T>* fibers = cores + off;
+    const unsigned grid =
+        (unsigned)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
+    ProfScope ps(&P->prof, KIND_OUTER, st);
+    outer_adam_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(
+        fibers, p == 0 ? renv : lenv, p == 0 ? ridx : lidx, (const cx<T>*)C.vals, C.blk_off,
+        C.nblocks, mom, vel, a);
+    BFC_HIP_TRY(hipGetLastError());
+  } else {
+    cx<T>* slices = cores + off;
+    if (C.nitems > 0) {
+      ProfScope ps(&P->prof, KIND_INNER_IR, st);
+      if (C.group_by_row)
+        inner_ir_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(lenv, lidx, renv, ridx,
+                                                          (const cx<T>*)C.vals, C.sub_off,
+                                                          C.items, slices, (T*)P->adam_part);
+      else
+        inner_ir_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(lenv, lidx, renv, ridx,
+                                                          (const cx<T>*)C.vals, C.sub_off,
+                                                          C.items, slices, (T*)P->adam_part);
+      BFC_HIP_TRY(hipGetLastError());
+    }
+    ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
+    inner_adam_kernel<T, R><<<C.nblocks, 64, 0, st>>>(slices, (const T*)P->adam_part,
+                                                      C.tile_items, mom, vel, a);
+    BFC_HIP_TRY(hipGetLastError());
+  }
+  P->fused_res_valid = false;
   for (int q = 0; q < p && q < L; ++q) P->rlev[q].valid = false;
   for (int q = p + 1; q <= L + 1; ++q)
     if (q >= 2) P->llev[q].valid = false;
@@ -1555,6 +1731,12 @@ bfc_status dispatch(int prec, int r, Args... args) {
 template <typename T, int R>
 struct SweepF {
   static bfc_status run(Problem* P, int p, hipStream_t st) { return sweep_core_t<T, R>(P, p, st); }
+};
+template <typename T, int R>
+struct AdamF {
+  static bfc_status run(Problem* P, int p, const AdamArgs* a, hipStream_t st) {
+    return adam_core_t<T, R>(P, p, *a, st);
+  }
 };
 template <typename T, int R>
 struct PredictF {
@@ -1870,6 +2052,13 @@ size_t inner_partial_bytes(int prec, int r) {
 
 bfc_status launch_sweep_core(Problem* P, int core, hipStream_t st) {
   return dispatch<SweepF>(P->prec, P->r, P, core, st);
+}
+
+bfc_status launch_adam_core(Problem* P, int core, int t, double alpha, double beta1,
+                            double beta2, double sigma, hipStream_t st) {
+  const AdamArgs a{alpha, beta1, beta2, sigma, 1.0 - std::pow(beta1, (double)t),
+                   1.0 - std::pow(beta2, (double)t)};
+  return dispatch<AdamF>(P->prec, P->r, P, core, &a, st);
 }
 
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
