@@ -16,6 +16,7 @@ Besides the JSON fields of the bench contract the line carries:
                 time to a test error of 1e-3 (or the floor reached)
   bf16gram      the same sweep with the BF16-input Gram and refinement
   batching      the 64-instance workload swept in shared launches
+  adam          ADAM butterfly completion (Sec. 5.1.2) from the same start
   warm_start    Sec. 5.2's initial guess (low-rank completion, then the
                 randomized low-rank to butterfly conversion) against the
                 random start, on the 256-point workload and on this one
@@ -467,6 +468,7 @@ def main():
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the low-rank initial guess record")
+    ap.add_argument("--no-adam", action="store_true", help="skip the ADAM record")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -762,6 +764,30 @@ def main():
 
     if not args.no_batch:
         out["batching"] = batched_record(bfc, torch, dev, max(3, args.steps // 2))
+
+    def adam_record(iters=200, alpha=1e-2):
+        """Alg. "ADAM for Butterfly Completion" from the same random start:
+        time per iteration (the L+2 gradient and update steps, no residual)
+        and the test error after 20, 60 (the paper's t_max for the gradient
+        methods) and `iters` iterations."""
+        pa = bfc.init_cores(bfc.Config(n=w.n, L=w.L, r=w.r, precision=args.precision),
+                            rows_d, cols_d, vals_d, cores0, device=dev)
+        errs, spent = {}, 0.0
+        for t in range(1, iters + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bfc.adam_sweep(pa, t, alpha=alpha)
+            torch.cuda.synchronize()
+            spent += time.perf_counter() - t0
+            if t in (20, 60, iters):
+                errs[f"test_err_at_{t}"] = bfc.relative_error(pa, trows_d, tcols_d, tvals_d)
+        pa.close()
+        return {"alpha": alpha, "beta1": 0.9, "beta2": 0.999, "sigma": 1e-8,
+                "ms_per_iteration": round(1e3 * spent / iters, 4),
+                "entries_per_s": round(w.nnz * iters / spent, 1), **errs}
+
+    if not args.no_adam:
+        out["adam"] = adam_record()
 
     if not args.no_warm:
         out["warm_start"] = [
