@@ -17,6 +17,7 @@ Besides the JSON fields of the bench contract the line carries:
   bf16gram      the same sweep with the BF16-input Gram and refinement
   batching      the 64-instance workload swept in shared launches
   adam          ADAM butterfly completion (Sec. 5.1.2) from the same start
+  radon         the Radon-transform operator (Sec. 6.3) through the same sweep
   warm_start    Sec. 5.2's initial guess (low-rank completion, then the
                 randomized low-rank to butterfly conversion) against the
                 random start, on the 256-point workload and on this one
@@ -469,6 +470,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the low-rank initial guess record")
     ap.add_argument("--no-adam", action="store_true", help="skip the ADAM record")
+    ap.add_argument("--no-radon", action="store_true", help="skip the Radon-operator record")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -788,6 +790,32 @@ def main():
 
     if not args.no_adam:
         out["adam"] = adam_record()
+
+    def radon_record(sweeps=20):
+        """The Radon-transform operator of Sec. 6.3 on the 1024-point
+        instance (c = 4, r = 8, 30 n log2 n entries) through the same sweep in
+        this precision: throughput of steps timed as the headline (sweep plus
+        train residual) and the test error
+        after each of `sweeps` sweeps from the random start."""
+        wr = make_workload("radon-1024")
+        pr = bfc.init_cores(bfc.Config(n=wr.n, L=wr.L, r=wr.r, precision=args.precision),
+                            wr.rows, wr.cols, wr.vals, wr.cores0, device=dev)
+        secs, _, _, _ = timed_sweeps(bfc, torch, pr, 10, 2, False)
+        pr.close()
+        pr = bfc.init_cores(bfc.Config(n=wr.n, L=wr.L, r=wr.r, precision=args.precision),
+                            wr.rows, wr.cols, wr.vals, wr.cores0, device=dev)
+        te = []
+        for _ in range(sweeps):
+            bfc.sweep(pr)
+            te.append(bfc.relative_error(pr, wr.test_rows, wr.test_cols, wr.test_vals))
+        pr.close()
+        return {"workload": wr.name, "n": wr.n, "L": wr.L, "r": wr.r, "nnz": wr.nnz,
+                "entries_per_s": round(wr.nnz * 10 / secs, 1),
+                "ms_per_sweep": round(1e3 * secs / 10, 4),
+                "test_err_at_1": te[0], f"test_err_at_{sweeps}": te[-1]}
+
+    if not args.no_radon:
+        out["radon"] = radon_record()
 
     if not args.no_warm:
         out["warm_start"] = [

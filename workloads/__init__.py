@@ -8,6 +8,7 @@ from .generators import (  # noqa: F401
     WORKLOADS,
     batched_instances,
     gaussian_sketches,
+    radon_entries,
     random_lowrank,
     Workload,
     green_line_entries,

@@ -169,11 +169,27 @@ class Workload:
         return self.n >> self.L
 
 
+def radon_entries(n: int, rows, cols) -> np.ndarray:
+    """1D Radon transform operator of Sec. 6.3: t_ij = exp(2 pi i phi(x_i, y_j)),
+    phi(x, y) = x y + c(x) |y|, c(x) = (2 + sin(2 pi x)) / 8, with the 1-based
+    grid x_i = i / n, y_j = j - n / 2 (here i, j are 0-based indices, so the
+    paper's i is i + 1).  phi is evaluated modulo 1 in FP64 before the
+    exponential (|phi| reaches ~n/2, where the phase must keep its fraction)."""
+    x = (np.asarray(rows, dtype=np.float64) + 1.0) / n
+    y = np.asarray(cols, dtype=np.float64) + 1.0 - n / 2.0
+    c = (2.0 + np.sin(2.0 * np.pi * x)) / 8.0
+    # x y is exact to FP64 rounding; reduce the two terms modulo 1 separately
+    phase = np.mod(x * y, 1.0) + np.mod(c * np.abs(y), 1.0)
+    return np.exp(2j * np.pi * phase)
+
+
 def _entries(geometry, n, omega, rows, cols):
     if geometry == "line":
         return green_line_entries(n, omega, rows, cols)
     if geometry == "planes":
         return green_planes_entries(n, omega, rows, cols)
+    if geometry == "radon":
+        return radon_entries(n, rows, cols)
     raise ValueError(geometry)
 
 
@@ -185,6 +201,11 @@ WORKLOADS = {
     "green-line-16384": (16384, 8, 6, TWO_PI * 256, "line", 8, 10000, 2),
     # scale workload: 512 x 512 grids, wavelength of 8 grid cells
     "green-planes-262144": (262144, 12, 8, TWO_PI * 64, "planes", 4, 100000, 3),
+    # second operator family (Sec. 6.3): the 1D Radon transform, butterfly
+    # rank about 10 at 1e-3; leaf size c = 4, 30 n log2 n entries, r = 8 (the
+    # library's largest rank)
+    "radon-1024": (1024, 8, 8, 0.0, "radon", 30, 10000, 4),
+    "radon-256": (256, 6, 4, 0.0, "radon", 30, 1000, 5),
 }
 
 
