@@ -32,3 +32,10 @@ from .lowrank_to_butterfly import (  # noqa: F401
     sketch_shapes,
 )
 from .adam import adam_state, adam_sweep, adam_update, gradient  # noqa: F401
+from .adf import (  # noqa: F401
+    adf_core_step,
+    adf_sweep,
+    orthogonalize_left,
+    orthogonalize_right,
+    right_to_left_sweep,
+)
