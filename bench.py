@@ -17,6 +17,7 @@ Besides the JSON fields of the bench contract the line carries:
   bf16gram      the same sweep with the BF16-input Gram and refinement
   batching      the 64-instance workload swept in shared launches
   adam          ADAM butterfly completion (Sec. 5.1.2) from the same start
+  adf           ADF butterfly completion (Sec. 5.1.3) from the same start
   radon         the Radon-transform operator (Sec. 6.3) through the same sweep
   warm_start    Sec. 5.2's initial guess (low-rank completion, then the
                 randomized low-rank to butterfly conversion) against the
@@ -470,6 +471,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the low-rank initial guess record")
     ap.add_argument("--no-adam", action="store_true", help="skip the ADAM record")
+    ap.add_argument("--no-adf", action="store_true", help="skip the ADF record")
     ap.add_argument("--no-radon", action="store_true", help="skip the Radon-operator record")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
@@ -790,6 +792,30 @@ def main():
 
     if not args.no_adam:
         out["adam"] = adam_record()
+
+    def adf_record(iters=60):
+        """Alg. "ADF for Butterfly Completion" from the same random start: time
+        per iteration (right-to-left orthogonalization, then per core the
+        direction, the line search, the step and the left orthogonalization)
+        and the test error after 20 and `iters` (the paper's t_max for the
+        gradient methods) iterations."""
+        pa = bfc.init_cores(bfc.Config(n=w.n, L=w.L, r=w.r, precision=args.precision),
+                            rows_d, cols_d, vals_d, cores0, device=dev)
+        errs, spent = {}, 0.0
+        for t in range(1, iters + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bfc.adf_sweep(pa)
+            torch.cuda.synchronize()
+            spent += time.perf_counter() - t0
+            if t in (20, iters):
+                errs[f"test_err_at_{t}"] = bfc.relative_error(pa, trows_d, tcols_d, tvals_d)
+        pa.close()
+        return {"ms_per_iteration": round(1e3 * spent / iters, 4),
+                "entries_per_s": round(w.nnz * iters / spent, 1), **errs}
+
+    if not args.no_adf and (w.n >> w.L) <= 64:
+        out["adf"] = adf_record()
 
     def radon_record(sweeps=20):
         """The Radon-transform operator of Sec. 6.3 on the 1024-point

@@ -307,6 +307,28 @@ bfc_status bfc_adam_sweep(bfc_problem* p, int32_t t, double alpha, double beta1,
 bfc_status bfc_adam_reset(bfc_problem* p, void* hip_stream);
 
 /*
+ * One iteration of Alg. "ADF for Butterfly Completion" (Sec. 5.1.3) with the
+ * orthogonalization sweeps of App. A.3.  First a right-to-left sweep makes
+ * cores L+1 .. 1 right-orthogonal: each leaf block of Z^(L+2) (c x r) and
+ * each pair of inner slices that differ in the last column digit (an LQ of
+ * the r x 2r pair) keeps the orthonormal factor, the triangular one is
+ * multiplied into the previous core.  Then for p = 0..L+1: the direction
+ * N = sum_e conj(a_e)(t_e - x_e) per block (a fiber of an outer core, a
+ * slice of an inner core), the exact line-search step
+ * alpha = ||N||^2 / ||A N||^2 and Z <- Z + alpha N per block (a block whose
+ * A N vanishes keeps its values), and for p <= L the left orthogonalization
+ * of core p (leaf blocks of Z^1; inner slices paired over the row digit they
+ * consume, stacked 2r x r) with R multiplied into core p+1.  Every QR runs
+ * in FP64 (Householder, reflector sign exp(i arg x_1)); the sums over the
+ * observed entries run in the compute precision.  The factors' phases
+ * differ from other QR routines' by a diagonal unitary, which leaves the
+ * represented tensor and every step unchanged.  Asynchronous on hip_stream;
+ * uses the problem's ADAM work buffers (allocated at the first call).
+ * BFC_EINVAL unless r <= c = n / 2^L <= 64.
+ */
+bfc_status bfc_adf_sweep(bfc_problem* p, void* hip_stream);
+
+/*
  * Initial guess of Sec. 5.2: low-rank completion is a problem with L = 0
  * (x_ij = Z^1[i] . Z^2[j], rank R), run with the calls above; this call turns
  * its result X = A B^T into butterfly cores by Alg.

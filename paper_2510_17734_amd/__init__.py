@@ -39,4 +39,5 @@ from .api import (  # noqa: F401
     lowrank_to_butterfly,
     adam_sweep,
     adam_reset,
+    adf_sweep,
 )

@@ -57,6 +57,7 @@ EXPORTS = (
     "bfc_lowrank_to_butterfly",
     "bfc_adam_sweep",
     "bfc_adam_reset",
+    "bfc_adf_sweep",
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
@@ -145,6 +146,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_adam_sweep.restype = i32
     lib.bfc_adam_reset.argtypes = [P, vp]
     lib.bfc_adam_reset.restype = i32
+    lib.bfc_adf_sweep.argtypes = [P, vp]
+    lib.bfc_adf_sweep.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

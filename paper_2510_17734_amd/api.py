@@ -367,3 +367,10 @@ def adam_sweep(p: Problem, t: int, alpha: float = 1e-3, beta1: float = 0.9, beta
 def adam_reset(p: Problem, stream=None):
     """bfc_adam_reset: zero the ADAM moments (a new run starts at t = 1)."""
     _check(_lib.load().bfc_adam_reset(p.handle, _stream(stream)), "bfc_adam_reset")
+
+
+def adf_sweep(p: Problem, stream=None):
+    """bfc_adf_sweep: one iteration of ADF butterfly completion (a right-to-left
+    orthogonalization, then per core a line-searched steepest step and a left
+    orthogonalization into the next core)."""
+    _check(_lib.load().bfc_adf_sweep(p.handle, _stream(stream)), "bfc_adf_sweep")

@@ -299,6 +299,29 @@ bfc_status bfc_adam_sweep(bfc_problem* p, int32_t t, double alpha, double beta1,
   return BFC_OK;
 }
 
+bfc_status bfc_adf_sweep(bfc_problem* p, void* hip_stream) {
+  if (!p) {
+    set_error("null problem");
+    return BFC_EINVAL;
+  }
+  if (p->c > 64 || p->c < p->r) {
+    set_error("bfc_adf_sweep: the leaf blocks need r <= c = n / 2^L <= 64 rows");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t real = p->elem / 2;
+  if (p->L >= 1 && p->adam_part_items < p->max_items) {
+    if (p->adam_part) BFC_TRY(dev_free(p, p->adam_part));
+    p->adam_part = nullptr;
+    BFC_TRY(dev_alloc(p, &p->adam_part,
+                      (size_t)std::max(p->max_items, 1) * 2 * p->r * p->r * real));
+    p->adam_part_items = std::max(p->max_items, 1);
+  }
+  if (p->L >= 1 && !p->adf_dir)
+    BFC_TRY(dev_alloc(p, &p->adf_dir, ((size_t)2 << p->L) * p->r * p->r * p->elem));
+  return launch_adf_sweep(p, st);
+}
+
 bfc_status bfc_adam_reset(bfc_problem* p, void* hip_stream) {
   if (!p) {
     set_error("null problem");

@@ -166,6 +166,7 @@ struct Problem {
   void* adam_v = nullptr;
   void* adam_part = nullptr;
   int32_t adam_part_items = 0;
+  void* adf_dir = nullptr;           // ADF directions of an inner core's slices
   double* fused_res = nullptr;       // 2 per fiber of the last core: residual norms
   bool fused_res_valid = false;      // fused_res belongs to the current cores
   size_t red_len = 0;
@@ -229,6 +230,7 @@ bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols
 bfc_status launch_sweep_core(Problem* P, int core, hipStream_t st);
 bfc_status launch_adam_core(Problem* P, int core, int t, double alpha, double beta1,
                             double beta2, double sigma, hipStream_t st);
+bfc_status launch_adf_sweep(Problem* P, hipStream_t st);
 bfc_status build_items(Problem* P, int core, hipStream_t st);
 bfc_status dev_free(Problem* P, void* ptr);
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,

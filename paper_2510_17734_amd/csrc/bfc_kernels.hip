@@ -702,8 +702,9 @@ __global__ __launch_bounds__(64) void inner_gram_bf16_kernel(
 // res = t - v . rho and w += conj(rho) res, and g += conj(l) (x) w.  Column
 // groups share rho: u = S0 rho, res = t - l . u, w += conj(l) res,
 // g += w (x) conj(rho).  Output: ir_part[item][2 d] (re, im interleaved),
-// the wavefront's lanes summed in a fixed order.
-template <typename T, int R, int BYROW>
+// the wavefront's lanes summed in a fixed order.  ZT: the targets are taken
+// as zero, which gives -sum conj(a_e) (a_e . s0) (the Gram applied to s0).
+template <typename T, int R, int BYROW, bool ZT = false>
 __global__ __launch_bounds__(64) void inner_ir_kernel(
     const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv, const int32_t* ridx,
     const cx<T>* vals, const int32_t* sub_off, const WorkItem* items, const cx<T>* slices,
@@ -765,7 +766,7 @@ __global__ __launch_bounds__(64) void inner_ir_kernel(
         cx<T> x = {T(0), T(0)};
 #pragma unroll
         for (int k = 0; k < R; ++k) cfma(x, m[k], vv[g][k]);
-        const cx<T> res = {tt[g].x - x.x, tt[g].y - x.y};
+        const cx<T> res = ZT ? cx<T>{-x.x, -x.y} : cx<T>{tt[g].x - x.x, tt[g].y - x.y};
 #pragma unroll
         for (int k = 0; k < R; ++k) cfma_conj(w[k], vv[g][k], res);  // w += conj(v) res
       }
@@ -1640,6 +1641,490 @@ bfc_status adam_core_t(Problem* P, int p, const AdamArgs& a, hipStream_t st) {
   return BFC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// ADF for butterfly completion (Sec. 5.1.3, Alg. "ADF for Butterfly
+// Completion") with the orthogonalization sweeps of App. A.3.  QR factors are
+// taken in FP64 by one wavefront per block or slice pair (row i of the
+// factored matrix in lane i, at most 64 rows: leaf blocks of c <= 64 rows,
+// slice pairs of 2r rows).
+// ---------------------------------------------------------------------------
+constexpr int kQrCols = 8;  // the largest rank
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Reduced Householder QR of the nrows x r matrix whose row `lane` is a (rows
+// >= nrows zero; reflector beta = -exp(i arg x_j) ||x||).  On return lane i
+// holds row i of Q in q and, for i < r, row i of R in a (columns >= i).
+__device__ __attribute__((always_inline)) inline void wave_qr(double2 (&a)[kQrCols], int nrows,
+                                                              int r, double2 (&q)[kQrCols],
+                                                              int lane) {
+  const bool row = lane < nrows;
+  double2 U[kQrCols];
+#pragma unroll
+  for (int j = 0; j < kQrCols; ++j) {
+    U[j] = make_double2(0.0, 0.0);
+    if (j >= r) continue;
+    const bool below = row && lane >= j;
+    const double2 x = make_double2(below ? a[j].x : 0.0, below ? a[j].y : 0.0);
+    const double nx = sqrt(wsum(x.x * x.x + x.y * x.y));
+    if (!(nx > 0.0)) continue;
+    const double2 al = make_double2(__shfl(x.x, j), __shfl(x.y, j));
+    const double aa = sqrt(al.x * al.x + al.y * al.y);
+    const double px = aa > 0.0 ? al.x / aa : 1.0, py = aa > 0.0 ? al.y / aa : 0.0;
+    const double2 v = make_double2(lane == j ? al.x + px * nx : x.x, lane == j ? al.y + py * nx : x.y);
+    const double vn = sqrt(wsum(v.x * v.x + v.y * v.y));
+    const double2 u = make_double2(v.x / vn, v.y / vn);
+    U[j] = u;
+#pragma unroll
+    for (int col = j + 1; col < kQrCols; ++col) {
+      if (col >= r) continue;
+      const double2 w = make_double2(wsum(u.x * a[col].x + u.y * a[col].y),
+                                     wsum(u.x * a[col].y - u.y * a[col].x));
+      a[col].x -= 2.0 * (u.x * w.x - u.y * w.y);
+      a[col].y -= 2.0 * (u.x * w.y + u.y * w.x);
+    }
+    // column j becomes beta e_j
+    a[j] = make_double2(lane == j ? -px * nx : (lane < j ? a[j].x : 0.0),
+                        lane == j ? -py * nx : (lane < j ? a[j].y : 0.0));
+  }
+#pragma unroll
+  for (int c = 0; c < kQrCols; ++c) q[c] = make_double2(lane == c && c < r ? 1.0 : 0.0, 0.0);
+#pragma unroll
+  for (int j = kQrCols - 1; j >= 0; --j) {
+    if (j >= r) continue;
+#pragma unroll
+    for (int c = 0; c < kQrCols; ++c) {
+      if (c >= r) continue;
+      const double2 w = make_double2(wsum(U[j].x * q[c].x + U[j].y * q[c].y),
+                                     wsum(U[j].x * q[c].y - U[j].y * q[c].x));
+      q[c].x -= 2.0 * (U[j].x * w.x - U[j].y * w.y);
+      q[c].y -= 2.0 * (U[j].x * w.y + U[j].y * w.x);
+    }
+  }
+}
+
+// Row `lane` (< nrows) of a block stored row-major with r columns: x <- x F,
+// F (r x r) given by rows held in lanes 0..r-1 (trans: x <- x F^T).
+template <typename T>
+__device__ __attribute__((always_inline)) inline void rows_times(cx<T>* blk, int nrows, int r,
+                                                                 const double2 (&f)[kQrCols],
+                                                                 bool trans, int lane) {
+  double2 x[kQrCols], y[kQrCols];
+  const bool row = lane < nrows;
+#pragma unroll
+  for (int k = 0; k < kQrCols; ++k) {
+    const cx<T> v = (row && k < r) ? blk[(int64_t)lane * r + k] : cx<T>{T(0), T(0)};
+    x[k] = make_double2((double)v.x, (double)v.y);
+    y[k] = make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < kQrCols; ++i) {
+    if (i >= r) continue;
+#pragma unroll
+    for (int k = 0; k < kQrCols; ++k) {
+      if (k >= r) continue;
+      // F[i][k] from lane i
+      const double2 fik = make_double2(__shfl(f[k].x, i), __shfl(f[k].y, i));
+      // trans: y[i] += x[k] F[i][k]; else y[k] += x[i] F[i][k]
+      if (trans) {
+        y[i].x += x[k].x * fik.x - x[k].y * fik.y;
+        y[i].y += x[k].x * fik.y + x[k].y * fik.x;
+      } else {
+        y[k].x += x[i].x * fik.x - x[i].y * fik.y;
+        y[k].y += x[i].x * fik.y + x[i].y * fik.x;
+      }
+    }
+  }
+  if (!row) return;
+#pragma unroll
+  for (int k = 0; k < kQrCols; ++k)
+    if (k < r) blk[(int64_t)lane * r + k] = cx<T>{T(y[k].x), T(y[k].y)};
+}
+
+// Left-to-right: QR of leaf block ib of Z^1 (c rows), R absorbed from the
+// left into the slices (ib << 1) | b of core 1 (L >= 1) or, for L = 0, from
+// the right (transposed) into the rows of Z^2.
+template <typename T, int R>
+__global__ __launch_bounds__(64) void orth_z1_left_kernel(cx<T>* z1, cx<T>* next, int c, int L) {
+  const int ib = blockIdx.x, lane = threadIdx.x;
+  const bool row = lane < c;
+  cx<T>* blk = z1 + (int64_t)ib * c * R;
+  double2 a[kQrCols], q[kQrCols];
+#pragma unroll
+  for (int k = 0; k < kQrCols; ++k) {
+    const cx<T> v = (row && k < R) ? blk[(int64_t)lane * R + k] : cx<T>{T(0), T(0)};
+    a[k] = make_double2((double)v.x, (double)v.y);
+  }
+  wave_qr(a, c, R, q, lane);
+  if (row) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) blk[(int64_t)lane * R + k] = cx<T>{T(q[k].x), T(q[k].y)};
+  }
+  if (L == 0) {
+    rows_times<T>(next + (int64_t)ib * c * R, c, R, a, true, lane);
+    return;
+  }
+  // slices of core 1: new row i = sum_k R[i][k] slice row k, i.e. the slice's
+  // transpose times R^T: treat the slice's columns as rows
+  for (int b = 0; b < 2; ++b) {
+    cx<T>* sl = next + (int64_t)((ib << 1) | b) * R * R;
+    double2 col[kQrCols], out[kQrCols];
+    // lane i < R gathers column i of the slice: col[k] = slice[k][i]
+#pragma unroll
+    for (int k = 0; k < kQrCols; ++k) {
+      const cx<T> v = (lane < R && k < R) ? sl[k * R + lane] : cx<T>{T(0), T(0)};
+      col[k] = make_double2((double)v.x, (double)v.y);
+      out[k] = make_double2(0.0, 0.0);
+    }
+    // out (column lane of R S) [i] = sum_k R[i][k] S[k][lane]
+#pragma unroll
+    for (int i = 0; i < kQrCols; ++i) {
+      if (i >= R) continue;
+#pragma unroll
+      for (int k = 0; k < kQrCols; ++k) {
+        if (k >= R) continue;
+        const double2 rik = make_double2(__shfl(a[k].x, i), __shfl(a[k].y, i));
+        out[i].x += rik.x * col[k].x - rik.y * col[k].y;
+        out[i].y += rik.x * col[k].y + rik.y * col[k].x;
+      }
+    }
+    if (lane < R) {
+#pragma unroll
+      for (int i = 0; i < kQrCols; ++i)
+        if (i < R) sl[i * R + lane] = cx<T>{T(out[i].x), T(out[i].y)};
+    }
+  }
+}
+
+// Left-to-right for inner core m: pair pi of slices (k0, k1 = k0 | 2^m),
+// stacked along the left rank (lane beta r + i holds row i of slice k_beta);
+// R absorbed from the left into the slices (pi << 1) | b of core m+1, or for
+// m = L from the right (transposed) into the rows of Z^(L+2) block pi.
+template <typename T, int R>
+__global__ __launch_bounds__(64) void orth_inner_left_kernel(cx<T>* core, cx<T>* next, int m,
+                                                             int L, int c) {
+  const int pi = blockIdx.x, lane = threadIdx.x;
+  const bool row = lane < 2 * R;
+  const int beta = row ? lane / R : 0, i = row ? lane % R : 0;
+  const int64_t k0 = ((int64_t)(pi >> m) << (m + 1)) | (pi & ((1 << m) - 1));
+  cx<T>* sl = core + (k0 | ((int64_t)beta << m)) * R * R;
+  double2 a[kQrCols], q[kQrCols];
+#pragma unroll
+  for (int k = 0; k < kQrCols; ++k) {
+    const cx<T> v = (row && k < R) ? sl[i * R + k] : cx<T>{T(0), T(0)};
+    a[k] = make_double2((double)v.x, (double)v.y);
+  }
+  wave_qr(a, 2 * R, R, q, lane);
+  if (row) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) sl[i * R + k] = cx<T>{T(q[k].x), T(q[k].y)};
+  }
+  if (m == L) {
+    rows_times<T>(next + (int64_t)pi * c * R, c, R, a, true, lane);
+    return;
+  }
+  for (int b = 0; b < 2; ++b) {
+    cx<T>* s2 = next + (int64_t)((pi << 1) | b) * R * R;
+    double2 col[kQrCols], out[kQrCols];
+#pragma unroll
+    for (int k = 0; k < kQrCols; ++k) {
+      const cx<T> v = (lane < R && k < R) ? s2[k * R + lane] : cx<T>{T(0), T(0)};
+      col[k] = make_double2((double)v.x, (double)v.y);
+      out[k] = make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int ii = 0; ii < kQrCols; ++ii) {
+      if (ii >= R) continue;
+#pragma unroll
+      for (int k = 0; k < kQrCols; ++k) {
+        if (k >= R) continue;
+        const double2 rik = make_double2(__shfl(a[k].x, ii), __shfl(a[k].y, ii));
+        out[ii].x += rik.x * col[k].x - rik.y * col[k].y;
+        out[ii].y += rik.x * col[k].y + rik.y * col[k].x;
+      }
+    }
+    if (lane < R) {
+#pragma unroll
+      for (int ii = 0; ii < kQrCols; ++ii)
+        if (ii < R) s2[ii * R + lane] = cx<T>{T(out[ii].x), T(out[ii].y)};
+    }
+  }
+}
+
+// Right-to-left: QR of leaf block jb of Z^(L+2) (stored c x r), R^T absorbed
+// from the right into the slices (b << L) | jb of core L, or for L = 0 into
+// the rows of Z^1.
+template <typename T, int R>
+__global__ __launch_bounds__(64) void orth_zlast_right_kernel(cx<T>* zl, cx<T>* prev, cx<T>* z1,
+                                                              int c, int L) {
+  const int jb = blockIdx.x, lane = threadIdx.x;
+  const bool row = lane < c;
+  cx<T>* blk = zl + (int64_t)jb * c * R;
+  double2 a[kQrCols], q[kQrCols];
+#pragma unroll
+  for (int k = 0; k < kQrCols; ++k) {
+    const cx<T> v = (row && k < R) ? blk[(int64_t)lane * R + k] : cx<T>{T(0), T(0)};
+    a[k] = make_double2((double)v.x, (double)v.y);
+  }
+  wave_qr(a, c, R, q, lane);
+  if (row) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) blk[(int64_t)lane * R + k] = cx<T>{T(q[k].x), T(q[k].y)};
+  }
+  if (L == 0) {
+    rows_times<T>(z1 + (int64_t)jb * c * R, c, R, a, true, lane);
+    return;
+  }
+  for (int b = 0; b < 2; ++b)
+    rows_times<T>(prev + ((int64_t)b << L | jb) * R * R, R, R, a, true, lane);
+}
+
+// Right-to-left for inner core m: pair pi of slices (2 pi, 2 pi + 1) side by
+// side along the right rank; lane beta r + j holds column j of slice
+// k_beta (the transposed pair is factored by QR, an LQ of the pair); the L
+// factor (R^T) is absorbed from the right into the slices of core m-1 that
+// differ in bit m-1, or for m = 1 into the rows of Z^1 block pi.
+template <typename T, int R>
+__global__ __launch_bounds__(64) void orth_inner_right_kernel(cx<T>* core, cx<T>* prev, int m,
+                                                              int c) {
+  const int pi = blockIdx.x, lane = threadIdx.x;
+  const bool row = lane < 2 * R;
+  const int beta = row ? lane / R : 0, j = row ? lane % R : 0;
+  cx<T>* sl = core + ((int64_t)2 * pi + beta) * R * R;
+  double2 a[kQrCols], q[kQrCols];
+#pragma unroll
+  for (int k = 0; k < kQrCols; ++k) {
+    const cx<T> v = (row && k < R) ? sl[k * R + j] : cx<T>{T(0), T(0)};
+    a[k] = make_double2((double)v.x, (double)v.y);
+  }
+  wave_qr(a, 2 * R, R, q, lane);
+  if (row) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) sl[k * R + j] = cx<T>{T(q[k].x), T(q[k].y)};
+  }
+  if (m == 1) {
+    rows_times<T>(prev + (int64_t)pi * c * R, c, R, a, true, lane);
+    return;
+  }
+  const int hi = pi >> (m - 1), lo = pi & ((1 << (m - 1)) - 1);
+  for (int b = 0; b < 2; ++b) {
+    const int64_t kp = ((int64_t)((hi << 1) | b) << (m - 1)) | lo;
+    rows_times<T>(prev + kp * R * R, R, R, a, true, lane);
+  }
+}
+
+// ADF step of an outer core: 16 lanes per fiber; pass 1 forms the direction
+// N = sum conj(a_e) (t_e - z . a_e), pass 2 the norm ||A N||^2 over the
+// fiber's entries, and lane k < R moves element k by alpha N_k with
+// alpha = ||N||^2 / ||A N||^2 (the fiber keeps its values when A N = 0).
+template <typename T, int R>
+__global__ __launch_bounds__(kOuterThreads) void outer_adf_kernel(
+    cx<T>* fibers, const cx<T>* env, const int32_t* env_idx, const cx<T>* vals,
+    const int32_t* blk_off, int nblocks) {
+  const int sub = threadIdx.x & 15;
+  const int b = (int)((blockIdx.x * kOuterThreads + threadIdx.x) >> 4);
+  int e0 = 0, e1 = 0;
+  if (b < nblocks) {
+    e0 = blk_off[b];
+    e1 = blk_off[b + 1];
+  }
+  cx<T> z[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    z[k] = b < nblocks ? fibers[(int64_t)b * R + k] : cx<T>{T(0), T(0)};
+  T nx[R], ny[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) nx[k] = ny[k] = T(0);
+  for (int base = e0 + sub; base < e1; base += 16 * 4) {
+    int id[4], ent[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ent[q] = base + 16 * q;
+      id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+    }
+    cx<T> v[4][R], t[4];
+    gather_group<T, R, 4>(env, vals, id, ent, v, t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (id[q] < 0) continue;
+      cx<T> x = {T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < R; ++k) cfma(x, z[k], v[q][k]);
+      const cx<T> res = {t[q].x - x.x, t[q].y - x.y};
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        cx<T> h = {nx[k], ny[k]};
+        cfma_conj(h, v[q][k], res);
+        nx[k] = h.x;
+        ny[k] = h.y;
+      }
+    }
+  }
+  cx<T> N[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) N[k] = cx<T>{row16_sum(nx[k]), row16_sum(ny[k])};
+  double zz = 0.0;
+  for (int base = e0 + sub; base < e1; base += 16 * 4) {
+    int id[4], ent[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ent[q] = base + 16 * q;
+      id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+    }
+    cx<T> v[4][R], t[4];
+    gather_group<T, R, 4>(env, vals, id, ent, v, t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (id[q] < 0) continue;
+      cx<T> x = {T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < R; ++k) cfma(x, N[k], v[q][k]);
+      zz += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+    }
+  }
+  zz = row16_sum(zz);
+  if (b >= nblocks || sub >= R || !(zz > 0.0)) return;
+  double nn = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) nn += (double)N[k].x * (double)N[k].x + (double)N[k].y * (double)N[k].y;
+  const double alpha = nn / zz;
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (k == sub) {
+      sx = (double)N[k].x;
+      sy = (double)N[k].y;
+    }
+  const int64_t o = (int64_t)b * R + sub;
+  const cx<T> s = fibers[o];
+  fibers[o] = cx<T>{T((double)s.x + alpha * sx), T((double)s.y + alpha * sy)};
+}
+
+// ADF on an inner core, per slice: stage 1 sums the work items' vectors
+// sum conj(a)(t - x) into the direction N (dir); stage 2 sums the items'
+// -sum conj(a)(a . N), so ||A N||^2 = -Re <N, that>, and moves the slice by
+// alpha N, alpha = ||N||^2 / ||A N||^2 (kept when A N = 0).  One wavefront
+// per slice, thread k < D for element k; the norms are wavefront sums.
+template <typename T, int R>
+__global__ __launch_bounds__(64) void inner_adf_kernel(cx<T>* slices, cx<T>* dir, const T* part,
+                                                       const int32_t* tile_items, int stage) {
+  constexpr int D = R * R;
+  const int tile = blockIdx.x, k = threadIdx.x;
+  const int it0 = tile_items[tile], it1 = tile_items[tile + 1];
+  double gx = 0.0, gy = 0.0;
+  if (k < D)
+    for (int it = it0; it < it1; ++it) {
+      gx += (double)part[(int64_t)it * 2 * D + 2 * k];
+      gy += (double)part[(int64_t)it * 2 * D + 2 * k + 1];
+    }
+  const int64_t o = (int64_t)tile * D + k;
+  if (stage == 1) {
+    if (k < D) dir[o] = cx<T>{T(gx), T(gy)};
+    return;
+  }
+  cx<T> nv = k < D ? dir[o] : cx<T>{T(0), T(0)};
+  const double nn = wsum((double)nv.x * (double)nv.x + (double)nv.y * (double)nv.y);
+  const double zz = -wsum((double)nv.x * gx + (double)nv.y * gy);
+  if (k >= D || !(zz > 0.0)) return;
+  const double alpha = nn / zz;
+  const cx<T> s = slices[o];
+  slices[o] = cx<T>{T((double)s.x + alpha * (double)nv.x), T((double)s.y + alpha * (double)nv.y)};
+}
+
+template <typename T, int R>
+bfc_status adf_sweep_t(Problem* P, hipStream_t st) {
+  cx<T>* cores = (cx<T>*)P->cores;
+  const int L = P->L;
+  const int c = P->c;
+  const int64_t nb = (int64_t)1 << L;
+  auto off = [&](int p) -> int64_t {
+    return p == 0 ? 0 : (p == L + 1 ? last_off(P->n, L, R) : inner_off(P->n, L, R, p));
+  };
+  // right-to-left orthogonalization: cores L+1 .. 1
+  {
+    ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
+    orth_zlast_right_kernel<T, R><<<(unsigned)nb, 64, 0, st>>>(
+        cores + off(L + 1), L >= 1 ? cores + off(L) : nullptr, cores, c, L);
+    for (int m = L; m >= 1; --m)
+      orth_inner_right_kernel<T, R><<<(unsigned)nb, 64, 0, st>>>(cores + off(m),
+                                                                 cores + off(m - 1), m, c);
+    BFC_HIP_TRY(hipGetLastError());
+  }
+  invalidate_envs(P);
+  for (int p = 0; p <= L + 1; ++p) {
+    const CoreLayout& C = P->lay[p];
+    {
+      ProfScope ps(&P->prof, KIND_ENV, st);
+      BFC_TRY(ensure_right<T, R>(P, p, st));
+      BFC_TRY(ensure_left<T, R>(P, p, st));
+    }
+    const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R)
+                                 : (p <= L - 1 ? (const cx<T>*)P->rlev[p].vec : nullptr);
+    const int32_t* ridx = (p == L) ? C.cols : C.rnode;
+    const cx<T>* lenv = (p == 1) ? cores : (p >= 2 ? (const cx<T>*)P->llev[p].vec : nullptr);
+    const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
+    if (p == 0 || p == L + 1) {
+      const unsigned grid =
+          (unsigned)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
+      ProfScope ps(&P->prof, KIND_OUTER, st);
+      outer_adf_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(
+          cores + off(p), p == 0 ? renv : lenv, p == 0 ? ridx : lidx, (const cx<T>*)C.vals,
+          C.blk_off, C.nblocks);
+    } else {
+      cx<T>* slices = cores + off(p);
+      cx<T>* dir = (cx<T>*)P->adf_dir;
+      T* part = (T*)P->adam_part;
+      ProfScope ps(&P->prof, KIND_INNER_IR, st);
+      for (int stage = 1; stage <= 2; ++stage) {
+        if (C.nitems > 0) {
+          const cx<T>* s0 = stage == 1 ? slices : dir;
+          if (C.group_by_row) {
+            if (stage == 1)
+              inner_ir_kernel<T, R, 1, false><<<C.nitems, 64, 0, st>>>(
+                  lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, s0, part);
+            else
+              inner_ir_kernel<T, R, 1, true><<<C.nitems, 64, 0, st>>>(
+                  lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, s0, part);
+          } else {
+            if (stage == 1)
+              inner_ir_kernel<T, R, 0, false><<<C.nitems, 64, 0, st>>>(
+                  lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, s0, part);
+            else
+              inner_ir_kernel<T, R, 0, true><<<C.nitems, 64, 0, st>>>(
+                  lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, s0, part);
+          }
+        }
+        inner_adf_kernel<T, R><<<C.nblocks, 64, 0, st>>>(slices, dir, part, C.tile_items, stage);
+      }
+    }
+    BFC_HIP_TRY(hipGetLastError());
+    if (p <= L) {
+      ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
+      if (p == 0)
+        orth_z1_left_kernel<T, R><<<(unsigned)nb, 64, 0, st>>>(cores, cores + off(1), c, L);
+      else
+        orth_inner_left_kernel<T, R><<<(unsigned)nb, 64, 0, st>>>(cores + off(p),
+                                                                  cores + off(p + 1), p, L, c);
+      BFC_HIP_TRY(hipGetLastError());
+    }
+    // cores p and p+1 changed: right levels below p+1 and left levels above p
+    for (int q = 0; q <= p && q < L; ++q) P->rlev[q].valid = false;
+    for (int q = p + 1; q <= L + 1; ++q)
+      if (q >= 2) P->llev[q].valid = false;
+  }
+  P->fused_res_valid = false;
+  return BFC_OK;
+}
+
+template <typename T, int R>
+struct AdfF {
+  static bfc_status run(Problem* P, hipStream_t st) { return adf_sweep_t<T, R>(P, st); }
+};
+
 // Entries per block and block count of a residual over m entries (the block
 // partials fit the problem's reduction scratch).
 inline void residual_split(const Problem* P, int64_t m, int64_t& per, int64_t& nblk) {
@@ -2059,6 +2544,10 @@ bfc_status launch_adam_core(Problem* P, int core, int t, double alpha, double be
   const AdamArgs a{alpha, beta1, beta2, sigma, 1.0 - std::pow(beta1, (double)t),
                    1.0 - std::pow(beta2, (double)t)};
   return dispatch<AdamF>(P->prec, P->r, P, core, &a, st);
+}
+
+bfc_status launch_adf_sweep(Problem* P, hipStream_t st) {
+  return dispatch<AdfF>(P->prec, P->r, P, st);
 }
 
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
