@@ -39,3 +39,4 @@ from .adf import (  # noqa: F401
     orthogonalize_right,
     right_to_left_sweep,
 )
+from . import mlp  # noqa: F401
