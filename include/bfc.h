@@ -184,6 +184,40 @@ bfc_status bfc_residual_observed(bfc_problem* p, double out_sq[2], void* hip_str
 bfc_status bfc_get_cores(const bfc_problem* p, void* d_cores, void* hip_stream);
 bfc_status bfc_set_cores(bfc_problem* p, const void* d_cores, void* hip_stream);
 
+/*
+ * The same as bfc_set_cores from FP32 values: d_cores holds
+ * bfc_num_params(n, L, r) complex values as interleaved (re, im) floats in
+ * the bfc_get_cores layout (device, caller owned), e.g. the output of a
+ * network that proposes starting cores.  Asynchronous.
+ */
+bfc_status bfc_set_cores_f32(bfc_problem* p, const float* d_cores, void* hip_stream);
+
+/*
+ * Replace the observed values t_e, keeping the observed index pairs (and so
+ * every sorted layout built by bfc_init_cores): d_vals is device complex128,
+ * nnz values in the order the pairs were given to bfc_init_cores.  Used to
+ * fit the same sample of positions to another matrix.  Synchronizes
+ * hip_stream; BFC_ENONFINITE if a value is NaN or Inf (the layout then holds
+ * the given values, the caller should replace them).
+ */
+bfc_status bfc_set_values(bfc_problem* p, const void* d_vals, void* hip_stream);
+
+/*
+ * Gradient of phi = 1/2 ||P_Omega(X - T)||^2 (Sec. 5.1.2: eq.
+ * (grad_butterfly_1), (grad_butterfly_l), (grad_butterfly_last)) with respect
+ * to every core at the current cores, none of which moves: per core the
+ * Wirtinger gradient g = sum_e conj(a_e)(x_e - t_e) from the cached
+ * environments (phi(s + d) = phi(s) + Re<g, d> + O(|d|^2), so (Re g, Im g) is
+ * the gradient with respect to the real and imaginary parts).  Writes
+ * scale * g to d_grad in the bfc_get_cores layout as interleaved (re, im)
+ * floats (grad_fp64 = 0) or doubles (grad_fp64 != 0); device, caller owned.
+ * If loss is not NULL, *loss = scale * phi (host; synchronizes hip_stream).
+ * Sums run in the compute precision.  BFC_EINVAL for a NULL d_grad or a NaN
+ * scale.
+ */
+bfc_status bfc_loss_gradient(bfc_problem* p, float scale, void* d_grad, int32_t grad_fp64,
+                             double* loss, void* hip_stream);
+
 /* Synchronize hip_stream and report (and clear) pending solve failures. */
 bfc_status bfc_sync_status(bfc_problem* p, void* hip_stream);
 

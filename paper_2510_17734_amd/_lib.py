@@ -58,6 +58,14 @@ EXPORTS = (
     "bfc_adam_sweep",
     "bfc_adam_reset",
     "bfc_adf_sweep",
+    "bfc_set_cores_f32",
+    "bfc_set_values",
+    "bfc_loss_gradient",
+    "bfc_mlp_forward",
+    "bfc_mlp_backward",
+    "bfc_mlp_forward_bf16",
+    "bfc_mlp_to_bf16",
+    "bfc_mlp_adam",
 )
 
 KERNEL_KINDS = {"outer": 0, "inner_gram": 1, "inner_solve": 2, "residual": 3, "predict": 4,
@@ -148,6 +156,23 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_adam_reset.restype = i32
     lib.bfc_adf_sweep.argtypes = [P, vp]
     lib.bfc_adf_sweep.restype = i32
+    lib.bfc_set_cores_f32.argtypes = [P, vp, vp]
+    lib.bfc_set_cores_f32.restype = i32
+    lib.bfc_set_values.argtypes = [P, vp, vp]
+    lib.bfc_set_values.restype = i32
+    f = ctypes.c_float
+    lib.bfc_loss_gradient.argtypes = [P, f, vp, i32, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_loss_gradient.restype = i32
+    lib.bfc_mlp_forward.argtypes = [i64, i64, i64, vp, vp, vp, i32, vp, vp]
+    lib.bfc_mlp_forward.restype = i32
+    lib.bfc_mlp_backward.argtypes = [i64, i64, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.bfc_mlp_backward.restype = i32
+    lib.bfc_mlp_forward_bf16.argtypes = [i64, i64, i64, vp, vp, vp, i32, vp, vp, vp]
+    lib.bfc_mlp_forward_bf16.restype = i32
+    lib.bfc_mlp_to_bf16.argtypes = [i64, vp, vp, vp]
+    lib.bfc_mlp_to_bf16.restype = i32
+    lib.bfc_mlp_adam.argtypes = [i64, vp, vp, vp, vp, i32, f, f, f, f, vp]
+    lib.bfc_mlp_adam.restype = i32
     lib.bfc_last_error.argtypes = []
     lib.bfc_last_error.restype = ctypes.c_char_p
     _lib = lib

@@ -374,3 +374,115 @@ def adf_sweep(p: Problem, stream=None):
     orthogonalization, then per core a line-searched steepest step and a left
     orthogonalization into the next core)."""
     _check(_lib.load().bfc_adf_sweep(p.handle, _stream(stream)), "bfc_adf_sweep")
+
+
+def set_cores_f32(p: Problem, cores: torch.Tensor, stream=None):
+    """bfc_set_cores_f32: cores as interleaved (re, im) float32 on the device
+    (2 * num_params values, bfc_get_cores layout)."""
+    m = num_params(p.cfg.n, p.cfg.L, p.cfg.r)
+    if cores.dtype != torch.float32 or cores.numel() != 2 * m or not cores.is_contiguous():
+        raise ValueError("set_cores_f32 needs 2 * num_params contiguous float32 values")
+    _check(_lib.load().bfc_set_cores_f32(p.handle, _ptr(cores), _stream(stream)),
+           "bfc_set_cores_f32")
+
+
+def set_values(p: Problem, vals, stream=None):
+    """bfc_set_values: new observed values at the same index pairs (input order)."""
+    t = _dev_c128(vals, p.device)
+    if t.numel() != p.nnz:
+        raise ValueError("set_values needs one value per observed pair")
+    _check(_lib.load().bfc_set_values(p.handle, _ptr(t), _stream(stream)), "bfc_set_values")
+
+
+def loss_gradient(p: Problem, out: torch.Tensor | None = None, scale: float = 1.0,
+                  fp64: bool = False, stream=None):
+    """bfc_loss_gradient: (scale * gradient of phi w.r.t. every core as
+    interleaved (re, im) values, scale * phi)."""
+    m = num_params(p.cfg.n, p.cfg.L, p.cfg.r)
+    dt = torch.float64 if fp64 else torch.float32
+    if out is None:
+        out = torch.empty(2 * m, dtype=dt, device=p.device)
+    elif out.dtype != dt or out.numel() != 2 * m or not out.is_contiguous():
+        raise ValueError("loss_gradient output has the wrong type or size")
+    loss = ctypes.c_double()
+    _check(_lib.load().bfc_loss_gradient(p.handle, float(scale), _ptr(out), 1 if fp64 else 0,
+                                         ctypes.byref(loss), _stream(stream)),
+           "bfc_loss_gradient")
+    return out, loss.value
+
+
+def _f32(t: torch.Tensor, name: str):
+    if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    return t
+
+
+def _bf16(t: torch.Tensor, name: str):
+    if t.dtype != torch.int16 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous int16 (BF16 bits) device tensor")
+    return t
+
+
+def mlp_forward(X, W, b=None, act: int = 0, out=None, stream=None):
+    """bfc_mlp_forward: act(X W + b), FP32."""
+    m, k = X.shape
+    n = W.shape[1]
+    if W.shape[0] != k or (b is not None and b.numel() != n):
+        raise ValueError("mlp_forward: shapes do not match")
+    if out is None:
+        out = torch.empty(m, n, dtype=torch.float32, device=X.device)
+    _check(_lib.load().bfc_mlp_forward(m, k, n, _ptr(_f32(X, "X")), _ptr(_f32(W, "W")),
+                                       _ptr(None if b is None else _f32(b, "b")), int(act),
+                                       _ptr(_f32(out, "out")), _stream(stream)),
+           "bfc_mlp_forward")
+    return out
+
+
+def mlp_backward(X, W, Y, dY, act: int = 0, need_dX: bool = True, stream=None):
+    """bfc_mlp_backward: (dX or None, dW, db)."""
+    m, k = X.shape
+    n = W.shape[1]
+    dX = torch.empty(m, k, dtype=torch.float32, device=X.device) if need_dX else None
+    dW = torch.empty(k, n, dtype=torch.float32, device=X.device)
+    db = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(_lib.load().bfc_mlp_backward(m, k, n, _ptr(_f32(X, "X")), _ptr(_f32(W, "W")),
+                                        _ptr(None if Y is None else _f32(Y, "Y")),
+                                        _ptr(_f32(dY, "dY")), int(act), _ptr(dX), _ptr(dW),
+                                        _ptr(db), _stream(stream)),
+           "bfc_mlp_backward")
+    return dX, dW, db
+
+
+def mlp_to_bf16(t, stream=None):
+    """bfc_mlp_to_bf16: BF16 bits (round to nearest even) in an int16 tensor."""
+    out = torch.empty(t.shape, dtype=torch.int16, device=t.device)
+    _check(_lib.load().bfc_mlp_to_bf16(t.numel(), _ptr(_f32(t, "src")), _ptr(out),
+                                       _stream(stream)), "bfc_mlp_to_bf16")
+    return out
+
+
+def mlp_forward_bf16(Xh, Wh, b=None, act: int = 0, want_f32: bool = True,
+                     want_bf16: bool = False, stream=None):
+    """bfc_mlp_forward_bf16: (Y float32 or None, Yh BF16 bits or None)."""
+    m, k = Xh.shape
+    n = Wh.shape[1]
+    Y = torch.empty(m, n, dtype=torch.float32, device=Xh.device) if want_f32 else None
+    Yh = torch.empty(m, n, dtype=torch.int16, device=Xh.device) if want_bf16 else None
+    _check(_lib.load().bfc_mlp_forward_bf16(m, k, n, _ptr(_bf16(Xh, "Xh")),
+                                            _ptr(_bf16(Wh, "Wh")),
+                                            _ptr(None if b is None else _f32(b, "b")), int(act),
+                                            _ptr(Y), _ptr(Yh), _stream(stream)),
+           "bfc_mlp_forward_bf16")
+    return Y, Yh
+
+
+def mlp_adam(params, grads, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, stream=None):
+    """bfc_mlp_adam: one ADAM step in place."""
+    for x, nme in ((params, "params"), (grads, "grads"), (m, "m"), (v, "v")):
+        _f32(x, nme)
+        if x.numel() != params.numel():
+            raise ValueError("mlp_adam: sizes differ")
+    _check(_lib.load().bfc_mlp_adam(params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+                                    int(t), float(lr), float(beta1), float(beta2), float(eps),
+                                    _stream(stream)), "bfc_mlp_adam")

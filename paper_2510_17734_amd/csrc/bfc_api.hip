@@ -426,6 +426,48 @@ bfc_status bfc_set_cores(bfc_problem* p, const void* d_cores, void* hip_stream) 
   return launch_convert_cores(p, d_cores, nullptr, true, (hipStream_t)hip_stream);
 }
 
+bfc_status bfc_set_cores_f32(bfc_problem* p, const float* d_cores, void* hip_stream) {
+  if (!p || !d_cores) {
+    set_error("bad set_cores_f32 arguments");
+    return BFC_EINVAL;
+  }
+  return launch_cores_from_f32(p, d_cores, (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_set_values(bfc_problem* p, const void* d_vals, void* hip_stream) {
+  if (!p || (!d_vals && p->nnz > 0)) {
+    set_error("bad set_values arguments");
+    return BFC_EINVAL;
+  }
+  if (!p->bad_flag) BFC_TRY(dev_alloc(p, (void**)&p->bad_flag, 4));
+  return launch_set_values(p, d_vals, (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_loss_gradient(bfc_problem* p, float scale, void* d_grad, int32_t grad_fp64,
+                             double* loss, void* hip_stream) {
+  if (!p || !d_grad || !(scale == scale)) {
+    set_error("bad loss_gradient arguments");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t real = p->elem / 2;
+  if (p->L >= 1 && p->adam_part_items < p->max_items) {
+    if (p->adam_part) BFC_TRY(dev_free(p, p->adam_part));
+    p->adam_part = nullptr;
+    BFC_TRY(dev_alloc(p, &p->adam_part,
+                      (size_t)std::max(p->max_items, 1) * 2 * p->r * p->r * real));
+    p->adam_part_items = std::max(p->max_items, 1);
+  }
+  if (!p->grad) BFC_TRY(dev_alloc(p, &p->grad, (size_t)p->nparams * p->elem));
+  BFC_TRY(launch_loss_gradient(p, scale, d_grad, grad_fp64 != 0, st));
+  if (loss) {
+    double sq[2];
+    BFC_TRY(bfc_residual_observed(p, sq, hip_stream));
+    *loss = 0.5 * (double)scale * sq[0];
+  }
+  return BFC_OK;
+}
+
 bfc_status bfc_sync_status(bfc_problem* p, void* hip_stream) {
   if (!p) {
     set_error("null problem");

@@ -81,6 +81,7 @@ struct CoreLayout {
   int32_t* rows = nullptr;     // entries sorted for this core
   int32_t* cols = nullptr;
   void* vals = nullptr;        // compute precision complex
+  int32_t* perm = nullptr;     // input position of every sorted entry
   int32_t* blk_off = nullptr;  // nblocks + 1
   // inner cores only
   int32_t group_by_row = 1;
@@ -167,6 +168,8 @@ struct Problem {
   void* adam_part = nullptr;
   int32_t adam_part_items = 0;
   void* adf_dir = nullptr;           // ADF directions of an inner core's slices
+  void* grad = nullptr;              // per-core gradients (bfc_loss_gradient)
+  int32_t* bad_flag = nullptr;       // non-finite value seen by bfc_set_values
   double* fused_res = nullptr;       // 2 per fiber of the last core: residual norms
   bool fused_res_valid = false;      // fused_res belongs to the current cores
   size_t red_len = 0;
@@ -231,6 +234,9 @@ bfc_status launch_sweep_core(Problem* P, int core, hipStream_t st);
 bfc_status launch_adam_core(Problem* P, int core, int t, double alpha, double beta1,
                             double beta2, double sigma, hipStream_t st);
 bfc_status launch_adf_sweep(Problem* P, hipStream_t st);
+bfc_status launch_set_values(Problem* P, const void* d_vals, hipStream_t st);
+bfc_status launch_cores_from_f32(Problem* P, const float* src, hipStream_t st);
+bfc_status launch_loss_gradient(Problem* P, float scale, void* out, int out_fp64, hipStream_t st);
 bfc_status build_items(Problem* P, int core, hipStream_t st);
 bfc_status dev_free(Problem* P, void* ptr);
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,

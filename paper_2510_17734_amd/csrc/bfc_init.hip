@@ -361,6 +361,8 @@ bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols
           idx, d_rows, d_cols, (const cx<float>*)vals_c, nnz, C.rows, C.cols,
           (cx<float>*)C.vals);
     BFC_HIP_TRY(hipGetLastError());
+    BFC_TRY(dev_alloc(P, (void**)&C.perm, nnz * 4));
+    BFC_HIP_TRY(hipMemcpyAsync(C.perm, idx, nnz * 4, hipMemcpyDeviceToDevice, st));
     block_offsets_kernel<<<grid_for(nnz), 256, 0, st>>>(keys, nnz, ext, C.nblocks, C.blk_off);
     BFC_HIP_TRY(hipGetLastError());
     // environment nodes of the sorted entries: right level p (p < L) and

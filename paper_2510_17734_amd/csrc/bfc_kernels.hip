@@ -2594,6 +2594,208 @@ bfc_status launch_convert_cores(Problem* P, const void* src, void* dst, bool to_
   return BFC_OK;
 }
 
+template <typename T>
+__global__ void values_to_layout_kernel(const int32_t* perm, const double2* src, cx<T>* dst,
+                                        int64_t nnz, int32_t* bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const double2 v = src[perm[k]];
+  if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(bad, 1);
+  dst[k] = cx<T>{T(v.x), T(v.y)};
+}
+
+bfc_status launch_set_values(Problem* P, const void* d_vals, hipStream_t st) {
+  const int64_t nnz = P->nnz;
+  if (nnz == 0) return BFC_OK;
+  BFC_HIP_TRY(hipMemsetAsync(P->bad_flag, 0, 4, st));
+  for (int p = 0; p <= P->L + 1; ++p) {
+    const CoreLayout& C = P->lay[p];
+    if (P->prec == BFC_C128)
+      values_to_layout_kernel<double><<<grid_for(nnz), 256, 0, st>>>(
+          C.perm, (const double2*)d_vals, (cx<double>*)C.vals, nnz, P->bad_flag);
+    else
+      values_to_layout_kernel<float><<<grid_for(nnz), 256, 0, st>>>(
+          C.perm, (const double2*)d_vals, (cx<float>*)C.vals, nnz, P->bad_flag);
+    BFC_HIP_TRY(hipGetLastError());
+  }
+  P->fused_res_valid = false;
+  int32_t bad = 0;
+  BFC_HIP_TRY(hipMemcpyAsync(&bad, P->bad_flag, 4, hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  if (bad) {
+    set_error("bfc_set_values: a value is NaN or Inf (the layout now holds it)");
+    return BFC_ENONFINITE;
+  }
+  return BFC_OK;
+}
+
+template <typename T>
+__global__ void cores_from_f32_kernel(const float2* src, cx<T>* dst, int64_t m) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) dst[k] = {T(src[k].x), T(src[k].y)};
+}
+
+bfc_status launch_cores_from_f32(Problem* P, const float* src, hipStream_t st) {
+  const int64_t m = P->nparams;
+  invalidate_envs(P);
+  if (P->prec == BFC_C128)
+    cores_from_f32_kernel<double><<<grid_for(m), 256, 0, st>>>((const float2*)src,
+                                                               (cx<double>*)P->cores, m);
+  else
+    cores_from_f32_kernel<float><<<grid_for(m), 256, 0, st>>>((const float2*)src,
+                                                              (cx<float>*)P->cores, m);
+  BFC_HIP_TRY(hipGetLastError());
+  return BFC_OK;
+}
+
+// Gradient of an outer core: 16 lanes per fiber sum conj(a_e)(x_e - t_e);
+// lane k < R writes element k.
+template <typename T, int R>
+__global__ __launch_bounds__(kOuterThreads) void outer_grad_kernel(
+    const cx<T>* fibers, const cx<T>* env, const int32_t* env_idx, const cx<T>* vals,
+    const int32_t* blk_off, int nblocks, cx<T>* grad) {
+  const int sub = threadIdx.x & 15;
+  const int b = (int)((blockIdx.x * kOuterThreads + threadIdx.x) >> 4);
+  int e0 = 0, e1 = 0;
+  if (b < nblocks) {
+    e0 = blk_off[b];
+    e1 = blk_off[b + 1];
+  }
+  cx<T> z[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    z[k] = b < nblocks ? fibers[(int64_t)b * R + k] : cx<T>{T(0), T(0)};
+  T gx[R], gy[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) gx[k] = gy[k] = T(0);
+  for (int base = e0 + sub; base < e1; base += 16 * 4) {
+    int id[4], ent[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ent[q] = base + 16 * q;
+      id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+    }
+    cx<T> v[4][R], t[4];
+    gather_group<T, R, 4>(env, vals, id, ent, v, t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (id[q] < 0) continue;
+      cx<T> x = {T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < R; ++k) cfma(x, z[k], v[q][k]);
+      const cx<T> res = {x.x - t[q].x, x.y - t[q].y};
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        cx<T> h = {gx[k], gy[k]};
+        cfma_conj(h, v[q][k], res);
+        gx[k] = h.x;
+        gy[k] = h.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    gx[k] = row16_sum(gx[k]);
+    gy[k] = row16_sum(gy[k]);
+  }
+  if (b >= nblocks || sub >= R) return;
+  cx<T> g = {T(0), T(0)};
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (k == sub) g = cx<T>{gx[k], gy[k]};
+  grad[(int64_t)b * R + sub] = g;
+}
+
+// Gradient of an inner slice: minus the sum of its work items' vectors
+// sum conj(a)(t - x), in a fixed order (thread k for element k).
+template <typename T, int R>
+__global__ __launch_bounds__(64) void inner_grad_kernel(const T* part, const int32_t* tile_items,
+                                                        cx<T>* grad) {
+  constexpr int D = R * R;
+  const int tile = blockIdx.x, k = threadIdx.x;
+  if (k >= D) return;
+  const int it0 = tile_items[tile], it1 = tile_items[tile + 1];
+  double gx = 0.0, gy = 0.0;
+  for (int it = it0; it < it1; ++it) {
+    gx -= (double)part[(int64_t)it * 2 * D + 2 * k];
+    gy -= (double)part[(int64_t)it * 2 * D + 2 * k + 1];
+  }
+  grad[(int64_t)tile * D + k] = cx<T>{T(gx), T(gy)};
+}
+
+template <typename T, typename O>
+__global__ void grad_out_kernel(const cx<T>* g, O* out, int64_t m, float scale) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  out[2 * k] = O((double)scale * (double)g[k].x);
+  out[2 * k + 1] = O((double)scale * (double)g[k].y);
+}
+
+template <typename T, int R>
+bfc_status loss_gradient_t(Problem* P, float scale, void* out, int out_fp64, hipStream_t st) {
+  const cx<T>* cores = (const cx<T>*)P->cores;
+  cx<T>* grad = (cx<T>*)P->grad;
+  const int L = P->L;
+  auto off = [&](int p) -> int64_t {
+    return p == 0 ? 0 : (p == L + 1 ? last_off(P->n, L, R) : inner_off(P->n, L, R, p));
+  };
+  for (int p = 0; p <= L + 1; ++p) {
+    const CoreLayout& C = P->lay[p];
+    {
+      ProfScope ps(&P->prof, KIND_ENV, st);
+      BFC_TRY(ensure_right<T, R>(P, p, st));
+      BFC_TRY(ensure_left<T, R>(P, p, st));
+    }
+    const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R)
+                                 : (p <= L - 1 ? (const cx<T>*)P->rlev[p].vec : nullptr);
+    const int32_t* ridx = (p == L) ? C.cols : C.rnode;
+    const cx<T>* lenv = (p == 1) ? cores : (p >= 2 ? (const cx<T>*)P->llev[p].vec : nullptr);
+    const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
+    if (p == 0 || p == L + 1) {
+      const unsigned grid =
+          (unsigned)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
+      ProfScope ps(&P->prof, KIND_OUTER, st);
+      outer_grad_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(
+          cores + off(p), p == 0 ? renv : lenv, p == 0 ? ridx : lidx, (const cx<T>*)C.vals,
+          C.blk_off, C.nblocks, grad + off(p));
+    } else {
+      ProfScope ps(&P->prof, KIND_INNER_IR, st);
+      T* part = (T*)P->adam_part;
+      if (C.nitems > 0) {
+        if (C.group_by_row)
+          inner_ir_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(lenv, lidx, renv, ridx,
+                                                            (const cx<T>*)C.vals, C.sub_off,
+                                                            C.items, cores + off(p), part);
+        else
+          inner_ir_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(lenv, lidx, renv, ridx,
+                                                            (const cx<T>*)C.vals, C.sub_off,
+                                                            C.items, cores + off(p), part);
+      }
+      inner_grad_kernel<T, R><<<C.nblocks, 64, 0, st>>>(part, C.tile_items, grad + off(p));
+    }
+    BFC_HIP_TRY(hipGetLastError());
+  }
+  const int64_t m = P->nparams;
+  if (out_fp64)
+    grad_out_kernel<T, double><<<grid_for(m), 256, 0, st>>>(grad, (double*)out, m, scale);
+  else
+    grad_out_kernel<T, float><<<grid_for(m), 256, 0, st>>>(grad, (float*)out, m, scale);
+  BFC_HIP_TRY(hipGetLastError());
+  return BFC_OK;
+}
+
+template <typename T, int R>
+struct LossGradF {
+  static bfc_status run(Problem* P, float scale, void* out, int out_fp64, hipStream_t st) {
+    return loss_gradient_t<T, R>(P, scale, out, out_fp64, st);
+  }
+};
+
+bfc_status launch_loss_gradient(Problem* P, float scale, void* out, int out_fp64,
+                                hipStream_t st) {
+  return dispatch<LossGradF>(P->prec, P->r, P, scale, out, out_fp64, st);
+}
+
 bfc_status launch_random_cores(Problem* P, uint64_t seed, hipStream_t st) {
   const int64_t m = P->nparams;
   invalidate_envs(P);

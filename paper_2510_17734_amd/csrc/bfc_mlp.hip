@@ -1,0 +1,255 @@
+// Dense layers of the warm-start network: forward, backward and ADAM for
+// FP32 training, a BF16-input forward for inference.  Every product is one
+// LDS-tiled kernel: 64 x 64 output tile per 256-thread workgroup, k-slabs of
+// 16 staged through LDS (loaded along whichever operand dimension is
+// contiguous), 4 x 4 outputs per thread, bias and activation fused into the
+// store.  The ReLU derivative of the backward pass is applied while the
+// gradient operand is loaded, so dZ = dY * (Y > 0) is never stored.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "bfc_common.h"
+#include "../../include/bfc_mlp.h"
+
+namespace bfc {
+namespace {
+
+constexpr int kTile = 64, kSlab = 16, kPad = 4;
+
+__device__ inline float load_as_float(const float* p, int64_t i) { return p[i]; }
+__device__ inline float load_as_float(const uint16_t* p, int64_t i) {
+  return __uint_as_float((uint32_t)p[i] << 16);
+}
+
+// round to nearest even (finite inputs)
+__device__ inline uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct Operand {
+  const void* p;
+  int64_t s_outer, s_k;  // element (outer, k) at p[outer * s_outer + k * s_k]
+  const float* mask;     // optional: the element counts only where mask > 0
+};
+
+// C[i][j] = act(sum_k A(i, k) B(j, k) + bias[j]); A is M x K, B is N x K as
+// (outer, k) operands.
+template <typename TI>
+__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, Operand A,
+                                                   Operand B, const float* bias, int act,
+                                                   float* C, uint16_t* Ch, int64_t ldc) {
+  __shared__ float As[kSlab][kTile + kPad];
+  __shared__ float Bs[kSlab][kTile + kPad];
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const int64_t i0 = (int64_t)blockIdx.y * kTile, j0 = (int64_t)blockIdx.x * kTile;
+  const TI* ap = (const TI*)A.p;
+  const TI* bp = (const TI*)B.p;
+  const bool a_outer_fast = A.s_outer == 1, b_outer_fast = B.s_outer == 1;
+  float acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+  for (int64_t k0 = 0; k0 < K; k0 += kSlab) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      // the contiguous dimension varies fastest across threads
+      const int o = a_outer_fast ? (e & (kTile - 1)) : (e >> 4);
+      const int kk = a_outer_fast ? (e >> 6) : (e & (kSlab - 1));
+      const int64_t gi = i0 + o, gk = k0 + kk;
+      float v = 0.f;
+      if (gi < M && gk < K) {
+        const int64_t idx = gi * A.s_outer + gk * A.s_k;
+        v = load_as_float(ap, idx);
+        if (A.mask && !(A.mask[idx] > 0.f)) v = 0.f;
+      }
+      As[kk][o] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int o = b_outer_fast ? (e & (kTile - 1)) : (e >> 4);
+      const int kk = b_outer_fast ? (e >> 6) : (e & (kSlab - 1));
+      const int64_t gj = j0 + o, gk = k0 + kk;
+      float v = 0.f;
+      if (gj < N && gk < K) {
+        const int64_t idx = gj * B.s_outer + gk * B.s_k;
+        v = load_as_float(bp, idx);
+        if (B.mask && !(B.mask[idx] > 0.f)) v = 0.f;
+      }
+      Bs[kk][o] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kSlab; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = As[kk][ty * 4 + u];
+        b[u] = Bs[kk][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t gi = i0 + ty * 4 + u;
+    if (gi >= M) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gj = j0 + tx * 4 + v;
+      if (gj >= N) continue;
+      float y = acc[u][v] + (bias ? bias[gj] : 0.f);
+      if (act == 1) y = y > 0.f ? y : 0.f;
+      if (C) C[gi * ldc + gj] = y;
+      if (Ch) Ch[gi * ldc + gj] = to_bf16(y);
+    }
+  }
+}
+
+// db[j] = sum_i dY[i][j] (* (Y[i][j] > 0) for ReLU), rows summed in order
+__global__ void colsum_kernel(int64_t m, int64_t n, const float* dY, const float* Y, float* db) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.f;
+  for (int64_t i = 0; i < m; ++i) {
+    const float g = dY[i * n + j];
+    if (!Y || Y[i * n + j] > 0.f) s += g;
+  }
+  db[j] = s;
+}
+
+__global__ void adam_kernel(int64_t count, float* p, const float* g, float* m, float* v,
+                            float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.f - b1) * gk;
+  const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+__global__ void to_bf16_kernel(int64_t count, const float* src, uint16_t* dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) dst[k] = to_bf16(src[k]);
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <typename TI>
+bfc_status gemm(int64_t M, int64_t N, int64_t K, Operand A, Operand B, const float* bias,
+                int act, float* C, uint16_t* Ch, int64_t ldc, hipStream_t st) {
+  if (M == 0 || N == 0) return BFC_OK;
+  const int64_t gx = (N + kTile - 1) / kTile, gy = (M + kTile - 1) / kTile;
+  if (gx > 0x7FFFFFFF || gy > 65535) {
+    set_error("bfc_mlp: matrix too large for one launch");
+    return BFC_EINVAL;
+  }
+  gemm_kernel<TI><<<dim3((unsigned)gx, (unsigned)gy), 256, 0, st>>>(M, N, K, A, B, bias, act, C,
+                                                                     Ch, ldc);
+  BFC_HIP_TRY(hipGetLastError());
+  return BFC_OK;
+}
+
+bool bad_sizes(int64_t m, int64_t k, int64_t n) { return m < 0 || k < 0 || n < 0; }
+
+}  // namespace
+}  // namespace bfc
+
+using namespace bfc;
+
+extern "C" {
+
+bfc_status bfc_mlp_forward(int64_t m, int64_t k, int64_t n, const float* X, const float* W,
+                           const float* b, int32_t act, float* Y, void* hip_stream) {
+  if (bad_sizes(m, k, n) || (act != 0 && act != 1) || (m * n > 0 && !Y) ||
+      (m * k > 0 && !X) || (k * n > 0 && !W)) {
+    set_error("bad bfc_mlp_forward arguments");
+    return BFC_EINVAL;
+  }
+  // A(i, kk) = X[i][kk]; B(j, kk) = W[kk][j]
+  return gemm<float>(m, n, k, Operand{X, k, 1, nullptr}, Operand{W, 1, n, nullptr}, b, act, Y,
+                     nullptr, n, (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_mlp_backward(int64_t m, int64_t k, int64_t n, const float* X, const float* W,
+                            const float* Y, const float* dY, int32_t act, float* dX, float* dW,
+                            float* db, void* hip_stream) {
+  const bool mn = m * n > 0;
+  if (bad_sizes(m, k, n) || (act != 0 && act != 1) || (act == 1 && mn && !Y) || (mn && !dY) ||
+      (dW && m * k > 0 && !X) || (dX && k * n > 0 && !W)) {
+    set_error("bad bfc_mlp_backward arguments");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const float* mask = act == 1 ? Y : nullptr;
+  // dW[kk][j] = sum_i X[i][kk] dZ[i][j]: A(kk, i) = X[i][kk], B(j, i) = dZ[i][j]
+  if (dW)
+    BFC_TRY(gemm<float>(k, n, m, Operand{X, 1, k, nullptr}, Operand{dY, 1, n, mask}, nullptr, 0,
+                        dW, nullptr, n, st));
+  // dX[i][kk] = sum_j dZ[i][j] W[kk][j]: A(i, j) = dZ[i][j], B(kk, j) = W[kk][j]
+  if (dX)
+    BFC_TRY(gemm<float>(m, k, n, Operand{dY, n, 1, mask}, Operand{W, n, 1, nullptr}, nullptr, 0,
+                        dX, nullptr, k, st));
+  if (db && n > 0) {
+    colsum_kernel<<<blocks_for(n, 256), 256, 0, st>>>(m, n, dY, mask, db);
+    BFC_HIP_TRY(hipGetLastError());
+  }
+  return BFC_OK;
+}
+
+bfc_status bfc_mlp_forward_bf16(int64_t m, int64_t k, int64_t n, const uint16_t* Xh,
+                                const uint16_t* Wh, const float* b, int32_t act, float* Y,
+                                uint16_t* Yh, void* hip_stream) {
+  if (bad_sizes(m, k, n) || (act != 0 && act != 1) || (m * n > 0 && !Y && !Yh) ||
+      (m * k > 0 && !Xh) || (k * n > 0 && !Wh)) {
+    set_error("bad bfc_mlp_forward_bf16 arguments");
+    return BFC_EINVAL;
+  }
+  return gemm<uint16_t>(m, n, k, Operand{Xh, k, 1, nullptr}, Operand{Wh, 1, n, nullptr}, b, act,
+                        Y, Yh, n, (hipStream_t)hip_stream);
+}
+
+bfc_status bfc_mlp_to_bf16(int64_t count, const float* src, uint16_t* dst, void* hip_stream) {
+  if (count < 0 || (count > 0 && (!src || !dst))) {
+    set_error("bad bfc_mlp_to_bf16 arguments");
+    return BFC_EINVAL;
+  }
+  if (count == 0) return BFC_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  to_bf16_kernel<<<blocks_for(count, 256), 256, 0, st>>>(count, src, dst);
+  BFC_HIP_TRY(hipGetLastError());
+  return BFC_OK;
+}
+
+bfc_status bfc_mlp_adam(int64_t count, float* params, const float* grads, float* m, float* v,
+                        int32_t t, float lr, float beta1, float beta2, float eps,
+                        void* hip_stream) {
+  if (count < 0 || t < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f) ||
+      (count > 0 && (!params || !grads || !m || !v))) {
+    set_error("bad bfc_mlp_adam arguments");
+    return BFC_EINVAL;
+  }
+  if (count == 0) return BFC_OK;
+  const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+  hipStream_t st = (hipStream_t)hip_stream;
+  adam_kernel<<<blocks_for(count, 256), 256, 0, st>>>(count, params, grads, m, v, lr, beta1,
+                                                      beta2, eps, c1, c2);
+  BFC_HIP_TRY(hipGetLastError());
+  return BFC_OK;
+}
+
+}  // extern "C"

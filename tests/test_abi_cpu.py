@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every declared symbol,
 and rejects bad arguments before touching a GPU."""
 import ctypes
+import glob
 import os
 import re
 
@@ -9,11 +10,11 @@ import pytest
 from paper_2510_17734_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bfc.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def _declared():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(bfc_[a-z_0-9]+)\s*\(", text)))
 

@@ -1,0 +1,173 @@
+"""GPU parity of the warm-start pieces against the oracle: the dense-layer
+kernels (FP32 forward and backward, ADAM, BF16 rounding and BF16 forward),
+the loss gradient over all cores (the gradient contractions of Sec. 5.1.2),
+replacing the observed values, and FP32 starting cores.
+
+Bars: FP32 layer outputs within 1e-5 of sum |x w| (+ |b|) per element (k
+FP32 products and sums, here k <= 4099); the ReLU mask of the backward pass
+is taken from the GPU's own forward output on both sides; BF16 bit patterns
+bit-exact; complex128 gradients within 1e-10 of the largest gradient entry,
+complex64 within 1e-4.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2510_17734_amd as bfc
+from workloads import green_line_entries, random_cores, sample_pairs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+SHAPES = [(37, 70, 131), (5, 4099, 512), (1, 512, 2000), (64, 64, 64), (65, 17, 3)]
+
+
+def _rand(shape, seed, scale=1.0):
+    g = torch.Generator().manual_seed(seed)
+    return (torch.randn(shape, generator=g, dtype=torch.float64) * scale).to(torch.float32)
+
+
+def _bound(X, W, b):
+    B = np.abs(X.astype(np.float64)) @ np.abs(W.astype(np.float64))
+    return B + (0 if b is None else np.abs(b)[None, :])
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "m%d_k%d_n%d" % s)
+@pytest.mark.parametrize("act", [0, 1])
+def test_forward_matches_oracle(shape, act):
+    m, k, n = shape
+    X, W, b = _rand((m, k), 1), _rand((k, n), 2, 1 / math.sqrt(k)), _rand((n,), 3)
+    Y = bfc.mlp_forward(X.to(DEV), W.to(DEV), b.to(DEV), act).cpu().numpy()
+    ref = oracle.mlp.forward(X.numpy(), W.numpy(), b.numpy(), act)
+    assert np.all(np.abs(Y - ref) <= 1e-5 * _bound(X.numpy(), W.numpy(), b.numpy()) + 1e-30)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "m%d_k%d_n%d" % s)
+@pytest.mark.parametrize("act", [0, 1])
+def test_backward_matches_oracle(shape, act):
+    m, k, n = shape
+    X, W, b = _rand((m, k), 4), _rand((k, n), 5, 1 / math.sqrt(k)), _rand((n,), 6)
+    dY = _rand((m, n), 7)
+    Xd, Wd = X.to(DEV), W.to(DEV)
+    Y = bfc.mlp_forward(Xd, Wd, b.to(DEV), act)
+    dX, dW, db = bfc.mlp_backward(Xd, Wd, Y, dY.to(DEV), act)
+    Yh = Y.cpu().numpy()
+    rX, rW, rb = oracle.mlp.backward(X.numpy(), W.numpy(), Yh, dY.numpy(), act)
+    mask = (Yh > 0) if act else np.ones_like(Yh, bool)
+    adY = np.abs(dY.numpy().astype(np.float64)) * mask
+    assert np.all(np.abs(dX.cpu().numpy() - rX) <= 1e-5 * (adY @ np.abs(W.numpy()).T) + 1e-30)
+    assert np.all(np.abs(dW.cpu().numpy() - rW) <= 1e-5 * (np.abs(X.numpy()).T @ adY) + 1e-30)
+    assert np.all(np.abs(db.cpu().numpy() - rb) <= 1e-5 * adY.sum(axis=0) + 1e-30)
+
+
+def test_backward_without_dx_and_empty_batch():
+    X, W, Y, dY = (torch.zeros(0, 8, device=DEV), _rand((8, 5), 1).to(DEV),
+                   torch.zeros(0, 5, device=DEV), torch.zeros(0, 5, device=DEV))
+    dX, dW, db = bfc.mlp_backward(X, W, Y, dY, 1, need_dX=False)
+    assert dX is None and torch.all(dW == 0) and torch.all(db == 0)
+
+
+def test_bf16_rounding_is_bit_exact():
+    g = torch.Generator().manual_seed(11)
+    x = torch.randn(100000, generator=g).to(torch.float32)
+    # exact ties: low 16 bits 0x8000 with both parities of bit 16
+    ties = (torch.randint(0, 1 << 15, (2000,), generator=g).to(torch.int32) << 17) | 0x8000
+    ties = (ties | (torch.arange(2000, dtype=torch.int32) % 2) << 16).view(torch.float32)
+    x = torch.cat([x, ties[torch.isfinite(ties)]])
+    got = bfc.mlp_to_bf16(x.to(DEV)).cpu().numpy().view(np.uint16)
+    assert np.array_equal(got, oracle.mlp.bf16_bits(x.numpy()))
+
+
+@pytest.mark.parametrize("shape", SHAPES[:3], ids=lambda s: "m%d_k%d_n%d" % s)
+def test_bf16_forward_matches_oracle(shape):
+    m, k, n = shape
+    X, W, b = _rand((m, k), 8), _rand((k, n), 9, 1 / math.sqrt(k)), _rand((n,), 10)
+    Xh, Wh = bfc.mlp_to_bf16(X.to(DEV)), bfc.mlp_to_bf16(W.to(DEV))
+    Y, Yh = bfc.mlp_forward_bf16(Xh, Wh, b.to(DEV), 1, want_f32=True, want_bf16=True)
+    Xr, Wr = oracle.mlp.bf16_round(X.numpy()), oracle.mlp.bf16_round(W.numpy())
+    ref = oracle.mlp.forward(Xr, Wr, b.numpy(), 1)
+    Yn = Y.cpu().numpy()
+    assert np.all(np.abs(Yn - ref) <= 1e-5 * _bound(Xr, Wr, b.numpy()) + 1e-30)
+    assert np.array_equal(Yh.cpu().numpy().view(np.uint16), oracle.mlp.bf16_bits(Yn))
+
+
+def test_adam_matches_oracle():
+    p, m, v = _rand((1000,), 1), torch.zeros(1000), torch.zeros(1000)
+    pd, md, vd = p.to(DEV), m.to(DEV), v.to(DEV)
+    rp, rm, rv = p.numpy().astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for t in range(1, 4):
+        g = _rand((1000,), 10 + t)
+        bfc.mlp_adam(pd, g.to(DEV), md, vd, t, 1e-3)
+        rp, rm, rv = oracle.mlp.adam_step(rp, g.numpy().astype(np.float64), rm, rv, t, 1e-3, 0.9,
+                                          0.999, 1e-8)
+    assert np.max(np.abs(pd.cpu().numpy() - rp)) <= 1e-6
+
+
+def _problem(n, L, r, nnz, seed, prec, reg_rel=1e-10):
+    rows, cols, _, _ = sample_pairs(n, nnz, 0, seed)
+    vals = green_line_entries(n, 2 * math.pi * (n >> L), rows, cols)
+    cores = random_cores(n, L, r, seed + 1, scale=float(np.sqrt(np.mean(np.abs(vals) ** 2) * r)))
+    prob = bfc.init_cores(bfc.Config(n=n, L=L, r=r, precision=prec, reg_rel=reg_rel), rows, cols,
+                          vals, cores, device=DEV)
+    return prob, rows, cols, vals, cores
+
+
+@pytest.mark.parametrize("shape", [(256, 4, 4, 8155), (128, 3, 5, 4000), (64, 0, 3, 1500)],
+                         ids=lambda s: "n%d_L%d_r%d" % s[:3])
+def test_loss_gradient_matches_oracle(shape):
+    n, L, r, nnz = shape
+    prob, rows, cols, vals, cores = _problem(n, L, r, nnz, 3, "c128")
+    g, loss = bfc.loss_gradient(prob, fp64=True, scale=0.5)
+    got = bfc.unflatten_cores(torch.view_as_complex(g.reshape(-1, 2)).cpu().numpy(), n, L, r)
+    ref = [0.5 * oracle.gradient(cores, p, rows, cols, vals, L) for p in range(L + 2)]
+    top = max(np.max(np.abs(x)) for x in ref)
+    for p in range(L + 2):
+        assert np.max(np.abs(got[p] - ref[p])) <= 1e-10 * top, p
+    assert abs(loss - 0.5 * oracle.objective(cores, rows, cols, vals, L)) <= 1e-10 * loss
+    # cores untouched; the same call twice gives the same bits
+    g2, _ = bfc.loss_gradient(prob, fp64=True, scale=0.5)
+    assert torch.equal(g, g2)
+    prob.close()
+    # complex64 problem, float32 output
+    prob, rows, cols, vals, cores = _problem(n, L, r, nnz, 3, "c64")
+    g, _ = bfc.loss_gradient(prob)
+    got = bfc.unflatten_cores(torch.view_as_complex(g.reshape(-1, 2)).cpu().numpy(), n, L, r)
+    for p in range(L + 2):
+        assert np.max(np.abs(got[p] - 2 * ref[p])) <= 1e-4 * 2 * top, p
+    prob.close()
+
+
+def test_set_values_and_f32_cores():
+    n, L, r, nnz = 256, 4, 4, 8155
+    prob, rows, cols, vals, cores = _problem(n, L, r, nnz, 5, "c128", reg_rel=1e-8)
+    new = green_line_entries(n, 2 * math.pi * 5, rows, cols) * (1 + 0.5j)
+    bfc.set_values(prob, new)
+    g, loss = bfc.loss_gradient(prob, fp64=True)
+    assert abs(loss - oracle.objective(cores, rows, cols, new, L)) <= 1e-10 * loss
+    got = bfc.unflatten_cores(torch.view_as_complex(g.reshape(-1, 2)).cpu().numpy(), n, L, r)
+    for p in (0, 2, L + 1):
+        ref = oracle.gradient(cores, p, rows, cols, new, L)
+        assert np.max(np.abs(got[p] - ref)) <= 1e-10 * np.max(np.abs(ref))
+    # a sweep sees the new values
+    bfc.sweep(prob)
+    ref = oracle.sweep(cores, rows, cols, new, L, reg_rel=1e-8)
+    X = oracle.dense_tensor_network(bfc.unflatten_cores(bfc.get_cores(prob).cpu().numpy(), n, L,
+                                                        r), L)
+    Xr = oracle.dense_tensor_network(ref, L)
+    assert np.linalg.norm(X - Xr) <= 1e-8 * np.linalg.norm(Xr)
+    # FP32 cores arrive as the same values
+    f = torch.view_as_real(torch.as_tensor(bfc.flatten_cores(cores))).reshape(-1)
+    f32 = f.to(torch.float32).to(DEV)
+    bfc.set_cores_f32(prob, f32)
+    back = torch.view_as_real(bfc.get_cores(prob)).reshape(-1).cpu()
+    assert torch.equal(back, f32.cpu().to(torch.float64))
+    bad = new.copy()
+    bad[17] = np.nan
+    with pytest.raises(bfc.BfcError):
+        bfc.set_values(prob, bad)
+    with pytest.raises(ValueError):
+        bfc.set_values(prob, new[:-1])
+    prob.close()

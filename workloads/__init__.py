@@ -18,4 +18,11 @@ from .generators import (  # noqa: F401
     num_params,
     random_cores,
     sample_pairs,
+    warm_params,
+    green_geom_entries,
+    observed_histogram,
+    WARM_N,
+    WARM_L,
+    WARM_R,
+    WARM_HIST_BINS,
 )

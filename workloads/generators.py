@@ -17,6 +17,10 @@ builds such inputs deterministically:
   has the complementary low-rank property.
 * ``random_cores``: i.i.d. circular complex Gaussian cores, the random
   initial guess of the ALS iteration.
+* ``warm_params`` / ``green_geom_entries`` / ``observed_histogram``: the
+  family of line-geometry operators (receiver line at distance d, shifted by
+  s, frequency w) the warm-start network is trained and evaluated on, and
+  the binned summary of an instance's observed entries it reads.
 
 Nothing here implements the completion method; both the CPU oracle and the
 GPU library receive these arrays as inputs.
@@ -254,3 +258,61 @@ def batched_instances(count: int = 64, base_seed: int = 100):
                         geometry="line", nnz=6 * n * _log2_int(n), ntest=1000,
                         seed=base_seed + k))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Family of operators for the learned warm start: the line geometry with the
+# receiver line moved (distance d, lateral shift s) and w drawn per instance.
+# ---------------------------------------------------------------------------
+WARM_N, WARM_L, WARM_R = 4096, 6, 6
+WARM_OMEGA_CYCLES = (32.0, 128.0)   # w / (2 pi)
+WARM_DIST = (0.75, 1.5)
+WARM_SHIFT = (-0.25, 0.25)
+WARM_HIST_BINS = 64
+
+
+def warm_params(seed: int):
+    """(w, d, s) of instance `seed`: PCG64(seed) uniforms, in that order, over
+    w / (2 pi) in [32, 128], d in [0.75, 1.5], s in [-0.25, 0.25]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.random(3)
+    w = TWO_PI * (WARM_OMEGA_CYCLES[0] + u[0] * (WARM_OMEGA_CYCLES[1] - WARM_OMEGA_CYCLES[0]))
+    d = WARM_DIST[0] + u[1] * (WARM_DIST[1] - WARM_DIST[0])
+    s = WARM_SHIFT[0] + u[2] * (WARM_SHIFT[1] - WARM_SHIFT[0])
+    return float(w), float(d), float(s)
+
+
+def green_geom_entries(n: int, omega: float, d: float, s: float, rows, cols):
+    """exp(+i w rho)/rho for sources (k/n, 0) and receivers (l/n + s, d).
+    Accepts numpy arrays, or torch tensors (computed in float64 on their
+    device, the same formula)."""
+    if hasattr(rows, "device") and not isinstance(rows, np.ndarray):
+        import torch
+        x = rows.to(torch.float64) / n
+        y = cols.to(torch.float64) / n + s
+        rho = torch.sqrt((x - y) ** 2 + d * d)
+        return torch.polar(1.0 / rho, omega * rho)
+    x = np.asarray(rows, dtype=np.float64) / n
+    y = np.asarray(cols, dtype=np.float64) / n + s
+    rho = np.sqrt((x - y) ** 2 + d * d)
+    return np.exp(1j * omega * rho) / rho
+
+
+def observed_histogram(n: int, rows, cols, vals, bins: int = WARM_HIST_BINS):
+    """bins x bins float32 array: the mean real part of the observed values
+    whose (row, column) falls in each cell of a uniform bins x bins grid over
+    the matrix (0 where a cell holds none).  numpy or torch inputs."""
+    if hasattr(rows, "device") and not isinstance(rows, np.ndarray):
+        import torch
+        cell = (rows.long() * bins // n) * bins + (cols.long() * bins // n)
+        tot = torch.zeros(bins * bins, dtype=torch.float64, device=rows.device)
+        cnt = torch.zeros(bins * bins, dtype=torch.float64, device=rows.device)
+        tot.index_add_(0, cell, vals.real.to(torch.float64))
+        cnt.index_add_(0, cell, torch.ones_like(tot[:1]).expand(cell.numel()))
+        return torch.where(cnt > 0, tot / cnt.clamp(min=1), tot).to(torch.float32).view(bins, bins)
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    cell = (rows * bins // n) * bins + (cols * bins // n)
+    tot = np.bincount(cell, weights=np.real(vals), minlength=bins * bins)
+    cnt = np.bincount(cell, minlength=bins * bins)
+    return np.where(cnt > 0, tot / np.maximum(cnt, 1), 0.0).astype(np.float32).reshape(bins, bins)
