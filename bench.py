@@ -19,6 +19,8 @@ Besides the JSON fields of the bench contract the line carries:
   adam          ADAM butterfly completion (Sec. 5.1.2) from the same start
   adf           ADF butterfly completion (Sec. 5.1.3) from the same start
   radon         the Radon-transform operator (Sec. 6.3) through the same sweep
+  learned_warm_start  the network that proposes starting cores, trained on
+                the method's own completions, against the Sec. 5.2 guess
   warm_start    Sec. 5.2's initial guess (low-rank completion, then the
                 randomized low-rank to butterfly conversion) against the
                 random start, on the 256-point workload and on this one
@@ -473,6 +475,11 @@ def main():
     ap.add_argument("--no-adam", action="store_true", help="skip the ADAM record")
     ap.add_argument("--no-adf", action="store_true", help="skip the ADF record")
     ap.add_argument("--no-radon", action="store_true", help="skip the Radon-operator record")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--learned-train", type=int, default=2000,
+                    help="training completions of the learned warm start")
+    ap.add_argument("--learned-epochs", type=int, default=60)
+    ap.add_argument("--learned-eval", type=int, default=200, help="held-out instances")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -816,6 +823,44 @@ def main():
 
     if not args.no_adf and (w.n >> w.L) <= 64:
         out["adf"] = adf_record()
+
+    def learned_record(n_train, epochs, n_eval):
+        """The learned warm start on the n = 4096 (L = 6, r = 6) operator
+        family: completions of n_train seeded operators by ALS (the training
+        data), `epochs` passes of FP32 training with the library's layer and
+        loss-gradient kernels, then sweeps and time to test error 1e-3 on
+        n_eval held-out operators (their own observed sets) from the network's
+        BF16 proposal, from the Sec. 5.2 initial guess and from a random
+        start."""
+        from paper_2510_17734_amd import warmstart as ws
+
+        log = lambda m: print(f"[learned] {m}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ds, lp, central = ws.make_dataset(n_train, 1000, device=dev, log=log)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        net = ws.WarmStartNet(ws.N_FEATURES, central.numel(), out_bias=central, device=dev)
+        hist = ws.train(net, ds, lp, epochs=epochs, log=log)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        lp.close()
+        res = ws.evaluate(net, list(range(900000, 900000 + n_eval)), device=dev, log=log)
+        summ = ws.summarize(res)
+        gain = None
+        if summ["learned"]["mean_sweeps_capped"]:
+            gain = round(summ["lowrank"]["mean_sweeps_capped"] /
+                         summ["learned"]["mean_sweeps_capped"], 3)
+        return {"n": ws.WARM_N, "L": ws.WARM_L, "r": ws.WARM_R, "nnz": ws.nnz_for(ws.WARM_N),
+                "train_instances": n_train, "epochs": epochs, "held_out": n_eval,
+                "network": "4 dense layers, width 512, ReLU; FP32 training, BF16 inference",
+                "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+                "train_loss_first_epoch": hist[0], "train_loss_last_epoch": hist[-1],
+                "target_test_err": 1e-3, "max_sweeps": 150, "starts": summ,
+                "sweeps_ratio_lowrank_over_learned": gain}
+
+    if not args.no_learned:
+        out["learned_warm_start"] = learned_record(args.learned_train, args.learned_epochs,
+                                                   args.learned_eval)
 
     def radon_record(sweeps=20):
         """The Radon-transform operator of Sec. 6.3 on the 1024-point
