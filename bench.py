@@ -19,6 +19,8 @@ Besides the JSON fields of the bench contract the line carries:
   adam          ADAM butterfly completion (Sec. 5.1.2) from the same start
   adf           ADF butterfly completion (Sec. 5.1.3) from the same start
   radon         the Radon-transform operator (Sec. 6.3) through the same sweep
+  green_c4      the paper's c = 4 Green's-function grid example (n = 16384,
+                L = 12) at rank 8
   learned_warm_start  the network that proposes starting cores, trained on
                 the method's own completions, against the Sec. 5.2 guess
   warm_start    Sec. 5.2's initial guess (low-rank completion, then the
@@ -476,6 +478,8 @@ def main():
     ap.add_argument("--no-adf", action="store_true", help="skip the ADF record")
     ap.add_argument("--no-radon", action="store_true", help="skip the Radon-operator record")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--no-green-c4", action="store_true",
+                    help="skip the c = 4 Green's-function grid record")
     ap.add_argument("--learned-train", type=int, default=2000,
                     help="training completions of the learned warm start")
     ap.add_argument("--learned-epochs", type=int, default=60)
@@ -887,6 +891,32 @@ def main():
 
     if not args.no_radon:
         out["radon"] = radon_record()
+
+    def green_c4_record(sweeps=20):
+        """The paper's n = 16384 Green's-function grid example (c = 4,
+        L = 12, w = sqrt(n) pi / 5, 6 r n log2 n entries) at rank 8 in this
+        precision: throughput of steps timed as the headline and the test
+        error after each of `sweeps` (the paper's t_max) sweeps from the
+        random start."""
+        wg = make_workload("green-planes-16384-c4")
+        pg = bfc.init_cores(bfc.Config(n=wg.n, L=wg.L, r=wg.r, precision=args.precision),
+                            wg.rows, wg.cols, wg.vals, wg.cores0, device=dev)
+        secs, _, _, _ = timed_sweeps(bfc, torch, pg, 10, 2, False)
+        pg.close()
+        pg = bfc.init_cores(bfc.Config(n=wg.n, L=wg.L, r=wg.r, precision=args.precision),
+                            wg.rows, wg.cols, wg.vals, wg.cores0, device=dev)
+        te = []
+        for _ in range(sweeps):
+            bfc.sweep(pg)
+            te.append(bfc.relative_error(pg, wg.test_rows, wg.test_cols, wg.test_vals))
+        pg.close()
+        return {"workload": wg.name, "n": wg.n, "L": wg.L, "c": wg.c, "r": wg.r, "nnz": wg.nnz,
+                "entries_per_s": round(wg.nnz * 10 / secs, 1),
+                "ms_per_sweep": round(1e3 * secs / 10, 4),
+                "test_err_at_1": te[0], f"test_err_at_{sweeps}": te[-1]}
+
+    if not args.no_green_c4:
+        out["green_c4"] = green_c4_record()
 
     if not args.no_warm:
         out["warm_start"] = [

@@ -209,6 +209,12 @@ WORKLOADS = {
     # rank about 10 at 1e-3; leaf size c = 4, 30 n log2 n entries, r = 8 (the
     # library's largest rank)
     "radon-1024": (1024, 8, 8, 0.0, "radon", 30, 10000, 4),
+    # the paper's Green's-function grids (Sec. 6.1): leaf size c = 4,
+    # w = sqrt(n) pi / 5 (ten points per wavelength); 66 n log2 n entries as
+    # in its n = 4096 example, 6 r n log2 n as in its n = 16384 example; rank 8
+    # (the library's largest; the paper's is 11)
+    "green-planes-4096-c4": (4096, 10, 8, 64 * math.pi / 5, "planes", 66, 10000, 6),
+    "green-planes-16384-c4": (16384, 12, 8, 128 * math.pi / 5, "planes", 48, 10000, 7),
     "radon-256": (256, 6, 4, 0.0, "radon", 30, 1000, 5),
 }
 
