@@ -801,13 +801,14 @@ __global__ __launch_bounds__(64) void inner_ir_kernel(
 // The work items' partial products are summed in a fixed order, so results do
 // not depend on scheduling.  K and the factor are row-major with an odd
 // leading dimension.  LDS: the real partial sum S is only needed to assemble
-// K and h, so the factor M reuses its space.
+// K and h, so the factor M reuses its space; K passes through registers (a
+// retry of the regularization ladder sums the partial products again), so a
+// slice holds one D x D complex array in LDS, not two.
 template <int R>
 struct SolveGeom {
   static constexpr int D = R * R;
   static constexpr int WP = InnerGeom<R>::WP;
   static constexpr int LD = (D % 2) ? D : D + 1;
-  static constexpr int K_BYTES = D * LD * 16;
   static constexpr int S_BYTES = WP * WP * 8;
   static constexpr int F_BYTES = (D + 1) * LD * 16;  // factor and its border row
   static constexpr int M_BYTES = (F_BYTES > S_BYTES ? F_BYTES : S_BYTES);
@@ -855,7 +856,6 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
 
   typedef SolveGeom<R> G;
   constexpr int D = G::D, WP = G::WP, LD = G::LD, NT = kSolveThreads;
-  __shared__ double2 K[D * LD];
   __shared__ __attribute__((aligned(16))) unsigned char mbuf[G::M_BYTES];
   __shared__ double2 panel[(D + 1) * kPanelLd];
   __shared__ double2 dinv[G::NP * kNb * kNb];
@@ -867,7 +867,9 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
   const int tile = blk;
   const int it0 = tile_items[tile], it1 = tile_items[tile + 1];
   if (it0 == it1) return;  // no observed entry in this slice: keep it
-  {
+  // S (in mbuf) = the sum of the slice's partial products; run again by a
+  // retry of the regularization ladder, since the factor overwrites S
+  auto sum_partials = [&]() {
     // items outer, 16-byte vectors inner, two items in flight per pass
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
     constexpr int VE = 16 / sizeof(T);
@@ -916,17 +918,13 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
 #pragma unroll
         for (int e = 0; e < VE; ++e) S[k * VE + e] = acc[q][e];
     }
-  }
+  };
+  sum_partials();
   __syncthreads();
-  for (int k = tid; k < D * D; k += NT) {
-    const int i = k / D, j = k % D;
-    K[i * LD + j] = inner_K<R>(S, WP, i, j);
-  }
   double2 h = make_double2(0.0, 0.0);
   if (tid < D) h = inner_h<R>(S, WP, tid);
-  __syncthreads();  // S is dead from here on; M takes its place
   double tr = 0.0;
-  for (int i = 0; i < D; ++i) tr += K[i * LD + i].x;  // same order in every thread
+  for (int i = 0; i < D; ++i) tr += inner_K<R>(S, WP, i, i).x;  // same order in every thread
   const double tau = tr / D;
   const double unit = fmax(reg_floor, 0x1p-53);
   double lam = fmax(reg_rel, D * reg_floor) * tau;
@@ -953,17 +951,35 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
   } else if (pass == 1 && tid < D) {
     ir_old[(int64_t)tile * D + tid] = slice[tid];
   }
+  // K = inner_K(S) is assembled into registers (entry k = tid + NT q of the
+  // D x LD layout) and written, regularized, over S as the factor M
+  constexpr int PK = (D * LD + NT - 1) / NT;
   bool ok = false;
   int attempt = 0;
   for (; attempt < (pass == 2 ? 1 : 4); ++attempt) {
     if (attempt > 0) {
       if (!(lam > 0.0)) break;
       lam = fmax(100.0 * lam, D * unit * tau);
+      __syncthreads();  // the failed factor is dead
+      sum_partials();
+      __syncthreads();
     }
-    for (int k = tid; k < D * LD; k += NT) {
-      double2 v = K[k];
-      if (k % LD == k / LD) v.x += lam;
-      M[k] = v;
+    double2 kreg[PK];
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+      const int k = tid + NT * q;
+      kreg[q] = make_double2(0.0, 0.0);
+      if (k < D * LD && k % LD < D) kreg[q] = inner_K<R>(S, WP, k / LD, k % LD);
+    }
+    __syncthreads();  // S is dead from here on; M takes its place
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+      const int k = tid + NT * q;
+      if (k < D * LD) {
+        double2 v = kreg[q];
+        if (k % LD == k / LD) v.x += lam;
+        M[k] = v;
+      }
     }
     if (tid < D) {  // border row: conj(right-hand side)
       double2 b = rhs;
