@@ -21,6 +21,7 @@ Besides the JSON fields of the bench contract the line carries:
   radon         the Radon-transform operator (Sec. 6.3) through the same sweep
   green_c4      the paper's c = 4 Green's-function grid example (n = 16384,
                 L = 12) at rank 8
+  scale         the 262144-point 2D-surface workload in the BF16-Gram mode
   learned_warm_start  the network that proposes starting cores, trained on
                 the method's own completions, against the Sec. 5.2 guess
   warm_start    Sec. 5.2's initial guess (low-rank completion, then the
@@ -480,6 +481,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-green-c4", action="store_true",
                     help="skip the c = 4 Green's-function grid record")
+    ap.add_argument("--no-scale", action="store_true",
+                    help="skip the 262144-point BF16-Gram scale record")
     ap.add_argument("--learned-train", type=int, default=2000,
                     help="training completions of the learned warm start")
     ap.add_argument("--learned-epochs", type=int, default=60)
@@ -917,6 +920,35 @@ def main():
 
     if not args.no_green_c4:
         out["green_c4"] = green_c4_record()
+
+    def scale_record(sweeps=20):
+        """The 2D-surface scale workload (n = 262144, L = 12, r = 8, two
+        512 x 512 grids in Morton order, 4 n log2 n entries) in the BF16-Gram
+        mode (BF16 inputs and FP32 sums for the slice Grams, FP64 solves and
+        one refinement): throughput of steps timed as the headline, and the
+        test error after each of `sweeps` sweeps from the random start."""
+        wg = make_workload("green-planes-262144")
+        cfg = bfc.Config(n=wg.n, L=wg.L, r=wg.r, precision="bf16gram")
+        pg = bfc.init_cores(cfg, wg.rows, wg.cols, wg.vals, wg.cores0, device=dev)
+        secs, _, _, _ = timed_sweeps(bfc, torch, pg, 5, 1, False)
+        pg.close()
+        pg = bfc.init_cores(cfg, wg.rows, wg.cols, wg.vals, wg.cores0, device=dev)
+        te, tr = [], []
+        for _ in range(sweeps):
+            bfc.sweep(pg)
+            te.append(bfc.relative_error(pg, wg.test_rows, wg.test_cols, wg.test_vals))
+            num, den = bfc.residual_observed(pg)
+            tr.append(math.sqrt(num / den))
+        pg.close()
+        return {"workload": wg.name, "precision": "bf16gram", "n": wg.n, "L": wg.L, "r": wg.r,
+                "nnz": wg.nnz, "params": 2 * wg.n * wg.r + wg.L * (2 << wg.L) * wg.r ** 2,
+                "entries_per_s": round(wg.nnz * 5 / secs, 1),
+                "ms_per_sweep": round(1e3 * secs / 5, 4),
+                "train_err_at_1": tr[0], f"train_err_at_{sweeps}": tr[-1],
+                "test_err_at_1": te[0], "test_err_at_10": te[9], f"test_err_at_{sweeps}": te[-1]}
+
+    if not args.no_scale:
+        out["scale"] = scale_record()
 
     if not args.no_warm:
         out["warm_start"] = [
