@@ -853,6 +853,8 @@ def main():
         lp.close()
         res = ws.evaluate(net, list(range(900000, 900000 + n_eval)), device=dev, log=log)
         summ = ws.summarize(res)
+        batched = ws.evaluate_batched(net, list(range(900000, 900000 + n_eval)), device=dev,
+                                      log=log)
         gain = None
         if summ["learned"]["mean_sweeps_capped"]:
             gain = round(summ["lowrank"]["mean_sweeps_capped"] /
@@ -863,6 +865,7 @@ def main():
                 "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
                 "train_loss_first_epoch": hist[0], "train_loss_last_epoch": hist[-1],
                 "target_test_err": 1e-3, "max_sweeps": 150, "starts": summ,
+                "batched_chunks_of_50": batched,
                 "sweeps_ratio_lowrank_over_learned": gain}
 
     if not args.no_learned:

@@ -21,7 +21,8 @@ with BF16 inputs and FP32 accumulation.  The last layer's bias starts at the
 completed cores of the family's central operator, so the untrained network
 already proposes a completion of a nearby operator.
 
-Every numeric step runs in libbfc.so; torch only holds device memory.
+The layers, the training step and the loss gradient run in libbfc.so; torch
+holds device memory and forms the input features.
 """
 from __future__ import annotations
 
@@ -284,4 +285,85 @@ def summarize(res, max_sweeps: int = 150):
             if rows else None,
             "mean_start_s": float(np.mean([x["start_s"] for x in rows])) if rows else None,
         }
+    return out
+
+
+def evaluate_batched(net: WarmStartNet, seeds, *, chunk: int = 50, target: float = 1e-3,
+                     max_sweeps: int = 150, device="cuda:0", log=None,
+                     starts=("learned", "lowrank")):
+    """The held-out instances swept together: per chunk of instances one
+    batch (bfc_batch_sweep: one launch per kernel kind for all of them), the
+    learned proposals inferred for the whole chunk at once.  Per start: the
+    time until every instance of a chunk reaches `target` (or the cap),
+    summed over chunks -- proposal, batch setup and sweeps, not the test-error
+    checks -- the same time until 90% of a chunk has reached it (the cap when
+    fewer do), and the instances reaching it."""
+    n, L, r = WARM_N, WARM_L, WARM_R
+    cfg = bfc.Config(n=n, L=L, r=r, precision="c64")
+    lr_cfg = bfc.Config(n=n, L=0, r=r, precision="c64", reg_rel=1e-6)
+    out = {s: {"time_s": 0.0, "reached": 0, "instances": 0, "sweeps": []} for s in starts}
+    for c0 in range(0, len(seeds), chunk):
+        insts, probs = [], []
+        for seed in seeds[c0:c0 + chunk]:
+            w, d, s_ = warm_params(seed)
+            rows, cols, trows, tcols = sample_pairs(n, nnz_for(n), 1000, seed + 500009)
+            vals = green_geom_entries(n, w, d, s_, rows, cols)
+            tvals = green_geom_entries(n, w, d, s_, trows, tcols)
+            rows_d = torch.as_tensor(rows, device=device)
+            cols_d = torch.as_tensor(cols, device=device)
+            vals_d = torch.as_tensor(vals, device=device)
+            insts.append({"seed": seed, "rows": rows, "cols": cols, "vals": vals,
+                          "w": w, "d": d, "s": s_,
+                          "hist": observed_histogram(n, rows_d, cols_d, vals_d),
+                          "sketches": gaussian_sketches(n, L, r, 4, seed=seed + 3),
+                          "test": (torch.as_tensor(trows, device=device),
+                                   torch.as_tensor(tcols, device=device),
+                                   torch.as_tensor(tvals, device=device))})
+            probs.append(bfc.init_cores(cfg, rows_d, cols_d, vals_d,
+                                        random_cores(n, L, r, seed + 7), device=device))
+        for start in starts:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if start == "learned":
+                X = torch.stack([features(x["w"], x["d"], x["s"], x["hist"]) for x in insts])
+                prop = net.infer_bf16(X.contiguous())
+                for i, p in enumerate(probs):
+                    bfc.set_cores_f32(p, prop[i])
+            else:
+                for x, p in zip(insts, probs):
+                    flat, _ = _lowrank_guess(x, lr_cfg, device)
+                    bfc.set_cores(p, flat)
+            b = bfc.batch_create(probs)
+            torch.cuda.synchronize()
+            spent = time.perf_counter() - t0
+            done = [None] * len(probs)
+            t90 = None
+            for sw in range(max_sweeps):
+                t1 = time.perf_counter()
+                bfc.batch_sweep(b)
+                torch.cuda.synchronize()
+                spent += time.perf_counter() - t1
+                for i, (x, p) in enumerate(zip(insts, probs)):
+                    if done[i] is None and bfc.relative_error(p, *x["test"]) <= target:
+                        done[i] = sw + 1
+                hits = sum(v is not None for v in done)
+                if t90 is None and hits >= 0.9 * len(done):
+                    t90 = spent
+                if hits == len(done):
+                    break
+            b.close()
+            o = out[start]
+            o["time_s"] += spent
+            o["time_to_90pct_s"] = (o.get("time_to_90pct_s") or 0.0) + (t90 if t90 else spent)
+            o["reached"] += sum(v is not None for v in done)
+            o["instances"] += len(done)
+            o["sweeps"].append(max(v or max_sweeps for v in done))
+        for p in probs:
+            p.close()
+        if log:
+            log(f"batched evaluation {min(c0 + chunk, len(seeds))}/{len(seeds)}")
+    for o in out.values():
+        o["time_s"] = round(o["time_s"], 4)
+        o["time_to_90pct_s"] = round(o.get("time_to_90pct_s", 0.0), 4)
+        o["sweeps_until_chunk_done"] = o.pop("sweeps")
     return out
