@@ -461,9 +461,13 @@ bfc_status bfc_loss_gradient(bfc_problem* p, float scale, void* d_grad, int32_t 
   if (!p->grad) BFC_TRY(dev_alloc(p, &p->grad, (size_t)p->nparams * p->elem));
   BFC_TRY(launch_loss_gradient(p, scale, d_grad, grad_fp64 != 0, st));
   if (loss) {
-    double sq[2];
-    BFC_TRY(bfc_residual_observed(p, sq, hip_stream));
-    *loss = 0.5 * (double)scale * sq[0];
+    // the residual pass alone: pending solve-failure counts stay for
+    // bfc_sync_status / bfc_residual_observed to report
+    double* dres = p->red + p->red_len;
+    BFC_TRY(launch_residual_observed(p, dres, st));
+    BFC_HIP_TRY(hipMemcpyAsync(p->red_host, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    BFC_HIP_TRY(hipStreamSynchronize(st));
+    *loss = 0.5 * (double)scale * p->red_host[0];
   }
   return BFC_OK;
 }
