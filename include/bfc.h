@@ -211,7 +211,8 @@ bfc_status bfc_set_values(bfc_problem* p, const void* d_vals, void* hip_stream);
  * the gradient with respect to the real and imaginary parts).  Writes
  * scale * g to d_grad in the bfc_get_cores layout as interleaved (re, im)
  * floats (grad_fp64 = 0) or doubles (grad_fp64 != 0); device, caller owned.
- * If loss is not NULL, *loss = scale * phi (host; synchronizes hip_stream).
+ * If loss is not NULL, *loss = scale * phi (host; synchronizes hip_stream;
+ * solve-failure counts of earlier sweeps stay pending for bfc_sync_status).
  * Sums run in the compute precision.  BFC_EINVAL for a NULL d_grad or a NaN
  * scale.
  */
