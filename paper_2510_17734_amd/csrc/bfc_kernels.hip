@@ -391,6 +391,11 @@ __global__ __launch_bounds__(kOuterThreads) void outer_update_kernel_batched(con
 // ---------------------------------------------------------------------------
 // entries of a subgroup whose environment loads are in flight together
 constexpr int kGatherGroup = 4;
+// Entries whose loads a lane issues together while it forms a subgroup's Gram
+// rows: four, or all eight of a subgroup at r = 8 in FP32, where the rows and
+// the MFMA accumulators allow one wavefront per SIMD anyway and the loads in
+// flight per wavefront are what hides the gather latency.
+constexpr int gram_gather_group(int r, int bytes) { return (r == 8 && bytes == 4) ? 8 : 4; }
 
 template <int R>
 struct InnerGeom {
@@ -414,6 +419,7 @@ __device__ __attribute__((always_inline)) inline void subgroup_rows(
     const int32_t* ridx, const cx<T>* vals, T (&arow)[InnerGeom<R>::W],
     T (&brow)[InnerGeom<R>::W]) {
   constexpr int D = R * R;
+  constexpr int GG = gram_gather_group(R, sizeof(T));
   T sum[D];
   T yx[R], yy[R];
   cx<T> shared_env[R];
@@ -440,18 +446,18 @@ __device__ __attribute__((always_inline)) inline void subgroup_rows(
     // entries in groups of G whose vector loads are issued together; a group
     // that no lane of the wavefront needs is skipped
 #pragma unroll
-    for (int g0 = 0; g0 < kSubgroup; g0 += kGatherGroup) {
+    for (int g0 = 0; g0 < kSubgroup; g0 += GG) {
       if (__ballot(e0 + g0 < e1) == 0) break;
-      int gid[kGatherGroup], ent[kGatherGroup];
+      int gid[GG], ent[GG];
 #pragma unroll
-      for (int g = 0; g < kGatherGroup; ++g) {
+      for (int g = 0; g < GG; ++g) {
         gid[g] = id[g0 + g];
         ent[g] = e0 + g0 + g;
       }
-      cx<T> v[kGatherGroup][R], t[kGatherGroup];
-      gather_group<T, R, kGatherGroup>(esrc, vals, gid, ent, v, t);
+      cx<T> v[GG][R], t[GG];
+      gather_group<T, R, GG>(esrc, vals, gid, ent, v, t);
 #pragma unroll
-      for (int g = 0; g < kGatherGroup; ++g) {
+      for (int g = 0; g < GG; ++g) {
         if (gid[g] < 0) continue;
         herm_acc<T, R>(sum, v[g]);
 #pragma unroll
