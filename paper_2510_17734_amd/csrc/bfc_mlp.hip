@@ -1,16 +1,19 @@
 // Dense layers of the warm-start network: forward, backward and ADAM for
 // FP32 training, a BF16-input forward for inference.  Every product is one
-// LDS-tiled kernel: 64 x 64 output tile per 256-thread workgroup, k-slabs of
-// 16 staged through LDS (loaded along whichever operand dimension is
-// contiguous), 4 x 4 outputs per thread, bias and activation fused into the
-// store.  The ReLU derivative of the backward pass is applied while the
-// gradient operand is loaded, so dZ = dY * (Y > 0) is never stored.
+// LDS-tiled MFMA kernel: a 64 x 64 output tile per 256-thread workgroup,
+// k-slabs of 16 staged through LDS (loaded along whichever operand dimension
+// is contiguous; BF16 operands widened to FP32 on the way, which is exact),
+// each wavefront a 32 x 32 quarter as 2 x 2 FP32 MFMA 16x16x4 blocks, bias and
+// activation fused into the store.  The ReLU derivative of the backward pass
+// is applied while the gradient operand is loaded, so dZ = dY * (Y > 0) is
+// never stored.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <string>
 
 #include "bfc_common.h"
+#include "bfc_device.h"
 #include "../../include/bfc_mlp.h"
 
 namespace bfc {
@@ -44,17 +47,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
                                                    float* C, uint16_t* Ch, int64_t ldc) {
   __shared__ float As[kSlab][kTile + kPad];
   __shared__ float Bs[kSlab][kTile + kPad];
-  const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // this wavefront's 32 x 32 quarter
   const int64_t i0 = (int64_t)blockIdx.y * kTile, j0 = (int64_t)blockIdx.x * kTile;
   const TI* ap = (const TI*)A.p;
   const TI* bp = (const TI*)B.p;
   const bool a_outer_fast = A.s_outer == 1, b_outer_fast = B.s_outer == 1;
-  float acc[4][4];
+  floatx4 acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+    for (int y = 0; y < 2; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
   for (int64_t k0 = 0; k0 < K; k0 += kSlab) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -86,35 +89,37 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
       Bs[kk][o] = v;
     }
     __syncthreads();
+    // MFMA 16x16x4: lane supplies A[i = lane % 16][k = lane / 16] and
+    // B[k = lane / 16][j = lane % 16] of its block
 #pragma unroll
-    for (int kk = 0; kk < kSlab; ++kk) {
-      float a[4], b[4];
+    for (int ks = 0; ks < kSlab; ks += 4) {
+      const int g = ks + (lane >> 4), col = lane & 15;
+      float xa[2], yb[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = As[kk][ty * 4 + u];
-        b[u] = Bs[kk][tx * 4 + u];
-      }
+      for (int x = 0; x < 2; ++x) xa[x] = As[g][wr * 32 + x * 16 + col];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int y = 0; y < 2; ++y) yb[y] = Bs[g][wc * 32 + y * 16 + col];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(a[u], b[v], acc[u][v]);
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<float>::step(xa[x], yb[y], acc[x][y]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t gi = i0 + ty * 4 + u;
-    if (gi >= M) continue;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t gj = j0 + tx * 4 + v;
-      if (gj >= N) continue;
-      float y = acc[u][v] + (bias ? bias[gj] : 0.f);
-      if (act == 1) y = y > 0.f ? y : 0.f;
-      if (C) C[gi * ldc + gj] = y;
-      if (Ch) Ch[gi * ldc + gj] = to_bf16(y);
-    }
-  }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = i0 + wr * 32 + x * 16 + Mfma<float>::out_row(lane, v);
+        const int64_t gj = j0 + wc * 32 + y * 16 + (lane & 15);
+        if (gi >= M || gj >= N) continue;
+        float o = acc[x][y][v] + (bias ? bias[gj] : 0.f);
+        if (act == 1) o = o > 0.f ? o : 0.f;
+        if (C) C[gi * ldc + gj] = o;
+        if (Ch) Ch[gi * ldc + gj] = to_bf16(o);
+      }
 }
 
 // db[j] = sum_i dY[i][j] (* (Y[i][j] > 0) for ReLU), rows summed in order
