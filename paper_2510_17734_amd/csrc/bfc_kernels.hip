@@ -1672,10 +1672,12 @@ bfc_status adam_core_t(Problem* P, int p, const AdamArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 constexpr int kQrCols = 8;  // the largest rank
 
+// Sum over the 64 lanes, the same value and order in every lane: DPP sums
+// within each row of 16 lanes, then the four row sums read as scalars (no
+// LDS round trips, which dominate the serial QR steps otherwise).
 __device__ inline double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v = row16_sum(v);
+  return (bcast_d(v, 0) + bcast_d(v, 16)) + (bcast_d(v, 32) + bcast_d(v, 48));
 }
 
 // Reduced Householder QR of the nrows x r matrix whose row `lane` is a (rows
@@ -1694,7 +1696,7 @@ __device__ __attribute__((always_inline)) inline void wave_qr(double2 (&a)[kQrCo
     const double2 x = make_double2(below ? a[j].x : 0.0, below ? a[j].y : 0.0);
     const double nx = sqrt(wsum(x.x * x.x + x.y * x.y));
     if (!(nx > 0.0)) continue;
-    const double2 al = make_double2(__shfl(x.x, j), __shfl(x.y, j));
+    const double2 al = make_double2(bcast_d(x.x, j), bcast_d(x.y, j));
     const double aa = sqrt(al.x * al.x + al.y * al.y);
     const double px = aa > 0.0 ? al.x / aa : 1.0, py = aa > 0.0 ? al.y / aa : 0.0;
     const double2 v = make_double2(lane == j ? al.x + px * nx : x.x, lane == j ? al.y + py * nx : x.y);
@@ -1750,7 +1752,7 @@ __device__ __attribute__((always_inline)) inline void rows_times(cx<T>* blk, int
     for (int k = 0; k < kQrCols; ++k) {
       if (k >= r) continue;
       // F[i][k] from lane i
-      const double2 fik = make_double2(__shfl(f[k].x, i), __shfl(f[k].y, i));
+      const double2 fik = make_double2(bcast_d(f[k].x, i), bcast_d(f[k].y, i));
       // trans: y[i] += x[k] F[i][k]; else y[k] += x[i] F[i][k]
       if (trans) {
         y[i].x += x[k].x * fik.x - x[k].y * fik.y;
@@ -1809,7 +1811,7 @@ __global__ __launch_bounds__(64) void orth_z1_left_kernel(cx<T>* z1, cx<T>* next
 #pragma unroll
       for (int k = 0; k < kQrCols; ++k) {
         if (k >= R) continue;
-        const double2 rik = make_double2(__shfl(a[k].x, i), __shfl(a[k].y, i));
+        const double2 rik = make_double2(bcast_d(a[k].x, i), bcast_d(a[k].y, i));
         out[i].x += rik.x * col[k].x - rik.y * col[k].y;
         out[i].y += rik.x * col[k].y + rik.y * col[k].x;
       }
@@ -1864,7 +1866,7 @@ __global__ __launch_bounds__(64) void orth_inner_left_kernel(cx<T>* core, cx<T>*
 #pragma unroll
       for (int k = 0; k < kQrCols; ++k) {
         if (k >= R) continue;
-        const double2 rik = make_double2(__shfl(a[k].x, ii), __shfl(a[k].y, ii));
+        const double2 rik = make_double2(bcast_d(a[k].x, ii), bcast_d(a[k].y, ii));
         out[ii].x += rik.x * col[k].x - rik.y * col[k].y;
         out[ii].y += rik.x * col[k].y + rik.y * col[k].x;
       }
