@@ -855,6 +855,7 @@ def main():
         summ = ws.summarize(res)
         batched = ws.evaluate_batched(net, list(range(900000, 900000 + n_eval)), device=dev,
                                       log=log)
+        prec = ws.precision_check(net, list(range(900000, 900000 + min(n_eval, 20))), device=dev)
         gain = None
         if summ["learned"]["mean_sweeps_capped"]:
             gain = round(summ["lowrank"]["mean_sweeps_capped"] /
@@ -866,6 +867,7 @@ def main():
                 "train_loss_first_epoch": hist[0], "train_loss_last_epoch": hist[-1],
                 "target_test_err": 1e-3, "max_sweeps": 150, "starts": summ,
                 "batched_chunks_of_50": batched,
+                "complex64_vs_complex128": prec,
                 "sweeps_ratio_lowrank_over_learned": gain}
 
     if not args.no_learned:

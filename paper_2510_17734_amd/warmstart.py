@@ -367,3 +367,42 @@ def evaluate_batched(net: WarmStartNet, seeds, *, chunk: int = 50, target: float
         o["time_to_90pct_s"] = round(o.get("time_to_90pct_s", 0.0), 4)
         o["sweeps_until_chunk_done"] = o.pop("sweeps")
     return out
+
+
+def precision_check(net: WarmStartNet, seeds, *, sweeps: int = 60, device="cuda:0"):
+    """Complex64 sweeps (FP32 contractions and Grams, FP64 solves) against
+    complex128 sweeps (FP64 throughout) from the same learned proposal, per
+    held-out instance: the test error after `sweeps` sweeps of each, and the
+    relative excess of the complex64 error over the complex128 one (negative
+    when complex64 ends lower)."""
+    n, L, r = WARM_N, WARM_L, WARM_R
+    rows_out = []
+    for seed in seeds:
+        w, d, s_ = warm_params(seed)
+        rows, cols, trows, tcols = sample_pairs(n, nnz_for(n), 1000, seed + 500009)
+        vals = green_geom_entries(n, w, d, s_, rows, cols)
+        tvals = green_geom_entries(n, w, d, s_, trows, tcols)
+        rows_d = torch.as_tensor(rows, device=device)
+        cols_d = torch.as_tensor(cols, device=device)
+        vals_d = torch.as_tensor(vals, device=device)
+        test = (torch.as_tensor(trows, device=device), torch.as_tensor(tcols, device=device),
+                torch.as_tensor(tvals, device=device))
+        x = features(w, d, s_, observed_histogram(n, rows_d, cols_d, vals_d))
+        prop = net.infer_bf16(x.reshape(1, -1).contiguous()).reshape(-1)
+        errs = {}
+        for prec in ("c64", "c128"):
+            p = bfc.init_cores(bfc.Config(n=n, L=L, r=r, precision=prec), rows_d, cols_d, vals_d,
+                               random_cores(n, L, r, seed + 7), device=device)
+            bfc.set_cores_f32(p, prop)
+            for _ in range(sweeps):
+                bfc.sweep(p)
+            errs[prec] = bfc.relative_error(p, *test)
+            p.close()
+        rows_out.append({"seed": seed, "c64": errs["c64"], "c128": errs["c128"],
+                         "excess": (errs["c64"] - errs["c128"]) / errs["c128"]})
+    ex = [x["excess"] for x in rows_out]
+    return {"instances": len(rows_out), "sweeps": sweeps,
+            "max_relative_excess": max(ex), "median_relative_excess": float(np.median(ex)),
+            "within_1e-4": sum(e <= 1e-4 for e in ex),
+            "median_c64_test_err": float(np.median([x["c64"] for x in rows_out])),
+            "median_c128_test_err": float(np.median([x["c128"] for x in rows_out]))}
