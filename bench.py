@@ -512,8 +512,8 @@ def main():
         mfma_summary(args.mfma_summary, args.bench_json, args.out, args.command)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design note only)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                                   "(sharding across GPUs is designed, not implemented)"}))
         sys.exit(2)
 
     import numpy as np
