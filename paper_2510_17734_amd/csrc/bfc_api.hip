@@ -7,6 +7,7 @@
 namespace bfc {
 
 size_t inner_partial_bytes(int prec, int r);
+size_t inner_factor_bytes(int r);
 
 namespace {
 thread_local std::string g_last_error;
@@ -200,6 +201,8 @@ bfc_status bfc_init_cores(const bfc_config* cfg, int64_t nnz, const int32_t* d_r
       if ((s = dev_alloc(P, (void**)&P->ir_lam, slices * sizeof(double))) != BFC_OK)
         return fail(s);
       if ((s = dev_alloc(P, &P->ir_old, slices * d * 2 * sizeof(float))) != BFC_OK)
+        return fail(s);
+      if ((s = dev_alloc(P, &P->ir_fac, slices * inner_factor_bytes(P->r))) != BFC_OK)
         return fail(s);
     }
   }

@@ -159,6 +159,7 @@ struct Problem {
   void* ir_part = nullptr;
   double* ir_lam = nullptr;
   void* ir_old = nullptr;
+  void* ir_fac = nullptr;            // BF16-Gram mode: each slice's factor, for the refinement
   double* red = nullptr;             // residual reduction scratch
   // ADAM (bfc_adam_sweep): first moments (complex), second moments (real),
   // both in the cores' layout, and per-item residual vectors; allocated at

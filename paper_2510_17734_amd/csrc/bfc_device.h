@@ -512,6 +512,50 @@ __device__ __attribute__((always_inline)) inline void serial_chol_solve(const do
   }
 }
 
+// Solve L y = b with the factor of wg_cholesky, by one wavefront: lane i
+// holds b_i in a register and ends with y_i.  Per diagonal block: broadcast
+// the block's running values, multiply by L_BB^-1, and subtract the block's
+// contribution from the rows below.  Reads only LDS (no writes, no barriers).
+__device__ __attribute__((always_inline)) inline void wave_fwd_solve(const double2* M,
+                                                                     const double2* dinv, int d,
+                                                                     int ld, double2& b,
+                                                                     int lane) {
+  const int li = lane < d ? lane : 0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < d; k0 += kNb) {
+    const int nb = d - k0 < kNb ? d - k0 : kNb;
+    const double2* Di = dinv + k0 * kNb;
+    double2 bb[kNb], s[kNb], l[kNb];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q)
+      bb[q] = q < nb ? make_double2(bcast_d(b.x, k0 + q), bcast_d(b.y, k0 + q))
+                     : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) {  // s[q] = sum_{p<=q} Di[q][p] bb[p], Di[q][q] real
+      const double dq = Di[q * kNb + q].x;
+      s[q] = make_double2(bb[q].x * dq, bb[q].y * dq);
+#pragma unroll
+      for (int p = 0; p < q; ++p) {
+        const double2 t = cmul(Di[q * kNb + p], bb[p]);
+        s[q].x += t.x;
+        s[q].y += t.y;
+      }
+      if (lane == k0 + q && q < nb) b = s[q];
+    }
+    // rows below the block: b_i -= sum_q L[i][k0+q] s_q (row li of the factor)
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) l[q] = q < nb ? M[li * ld + k0 + q] : make_double2(0.0, 0.0);
+    if (lane >= k0 + nb && lane < d) {
+#pragma unroll
+      for (int q = 0; q < kNb; ++q) {
+        const double2 t = cmul(l[q], s[q]);
+        b.x -= t.x;
+        b.y -= t.y;
+      }
+    }
+  }
+}
+
 // Deterministic sum over the 64 lanes of a wavefront (every lane gets the
 // same value, summed in the same order).
 template <typename T>

@@ -827,10 +827,12 @@ constexpr int kSolveThreads = 256;
 // h + lam s_old (regularization ladder), back-substitute, write the slice.
 // pass 0: the one solve of the FP64 / FP32-Gram modes.  pass 1: the first
 // solve of the BF16-Gram mode, which also keeps the slice's regularization
-// (ir_lam, negative when the slice is kept) and its old values (ir_old).
-// pass 2: the refinement, (K + lam I) delta = g + lam (s_old - s0) (ridge:
-// g - lam s0) with the same lam and g the entries' residual vector (ir_part,
-// per work item); the slice becomes s0 + delta.
+// (ir_lam, negative when the slice is kept), its old values (ir_old) and the
+// factor of K + lam I with its diagonal-block inverses (ir_fac).  pass 2: the
+// refinement, (K + lam I) delta = g + lam (s_old - s0) (ridge: g - lam s0)
+// with g the entries' residual vector (ir_part, per work item), solved with
+// the kept factor by one forward and one back substitution (no partial sums,
+// no factorization); the slice becomes s0 + delta.
 template <typename T>
 struct SolveArgs {
   cx<T>* slices;
@@ -844,7 +846,13 @@ struct SolveArgs {
   double* ir_lam;
   cx<T>* ir_old;
   const float* ir_part;
+  double2* ir_fac;  // per slice: the factor's D x LD rows, then the diagonal-block inverses
 };
+
+template <int R>
+constexpr int solve_factor_elems() {
+  return SolveGeom<R>::D * SolveGeom<R>::LD + SolveGeom<R>::NP * kNb * kNb;
+}
 
 template <typename T, int R>
 __device__ __attribute__((always_inline)) inline void inner_solve_body(const SolveArgs<T>& A, int blk) {
@@ -936,33 +944,15 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
   double lam = fmax(reg_rel, D * reg_floor) * tau;
   cx<T>* slice = slices + (int64_t)tile * D;
   double2 old = make_double2(0.0, 0.0);
-  if ((prox || pass == 2) && tid < D) old = make_double2((double)slice[tid].x, (double)slice[tid].y);
+  if (prox && tid < D) old = make_double2((double)slice[tid].x, (double)slice[tid].y);
   double2 rhs = h;  // right-hand side of the bordered factorization
-  if (pass == 2) {
-    lam = ir_lam[tile];
-    if (!(lam >= 0.0)) return;  // the first pass kept this slice
-    if (tid < D) {
-      // old holds s0 here; g from the work items in a fixed order
-      double gx = 0.0, gy = 0.0;
-      for (int it = it0; it < it1; ++it) {
-        gx += (double)ir_part[(int64_t)it * 2 * D + 2 * tid];
-        gy += (double)ir_part[(int64_t)it * 2 * D + 2 * tid + 1];
-      }
-      const cx<T> so = ir_old[(int64_t)tile * D + tid];
-      // residual of the regularized system at s0: g + lam (s_old - s0)
-      // (proximal) or g - lam s0 (ridge)
-      const double ox = prox ? (double)so.x : 0.0, oy = prox ? (double)so.y : 0.0;
-      rhs = make_double2(gx + lam * (ox - old.x), gy + lam * (oy - old.y));
-    }
-  } else if (pass == 1 && tid < D) {
-    ir_old[(int64_t)tile * D + tid] = slice[tid];
-  }
+  if (pass == 1 && tid < D) ir_old[(int64_t)tile * D + tid] = slice[tid];
   // K = inner_K(S) is assembled into registers (entry k = tid + NT q of the
   // D x LD layout) and written, regularized, over S as the factor M
   constexpr int PK = (D * LD + NT - 1) / NT;
   bool ok = false;
   int attempt = 0;
-  for (; attempt < (pass == 2 ? 1 : 4); ++attempt) {
+  for (; attempt < 4; ++attempt) {
     if (attempt > 0) {
       if (!(lam > 0.0)) break;
       lam = fmax(100.0 * lam, D * unit * tau);
@@ -989,7 +979,7 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
     }
     if (tid < D) {  // border row: conj(right-hand side)
       double2 b = rhs;
-      if (pass != 2 && prox) {
+      if (prox) {
         b.x += lam * old.x;
         b.y += lam * old.y;
       }
@@ -1010,6 +1000,11 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
     if (attempt > 0) atomicAdd(flags + 1, 1);
     if (pass == 1) ir_lam[tile] = lam;
   }
+  if (pass == 1) {  // keep the factor for the refinement pass
+    double2* F = A.ir_fac + (int64_t)tile * solve_factor_elems<R>();
+    for (int k = tid; k < D * LD; k += NT) F[k] = M[k];
+    for (int k = tid; k < G::NP * kNb * kNb; k += NT) F[D * LD + k] = dinv[k];
+  }
   if (tid >= 64) return;  // one wavefront solves; no barriers below
   double2 y = make_double2(0.0, 0.0);
   if (lane < D) {
@@ -1017,11 +1012,48 @@ __device__ __attribute__((always_inline)) inline void inner_solve_body(const Sol
     y = make_double2(t.x, -t.y);
   }
   wave_back_solve(M, dinv, D, LD, y, lane);
-  if (pass == 2) {
-    y.x += old.x;
-    y.y += old.y;
-  }
   if (lane < D) slice[lane] = {T(y.x), T(y.y)};
+}
+
+// Refinement of the BF16-Gram mode (the second pass): (K + lam I) delta =
+// g + lam (s_old - s0) (ridge: g - lam s0), g the entries' residual vector
+// (ir_part, per work item, summed in a fixed order), solved with the factor
+// the first pass kept (ir_fac) by one forward and one back substitution; the
+// slice becomes s0 + delta.  A slice the first pass kept (ir_lam < 0) or
+// without entries is left alone.
+template <typename T, int R>
+__global__ __launch_bounds__(kSolveThreads) void inner_refine_kernel(SolveArgs<T> A) {
+  typedef SolveGeom<R> G;
+  constexpr int D = G::D, LD = G::LD, NT = kSolveThreads;
+  __shared__ double2 Mf[D * LD];
+  __shared__ double2 dinv[G::NP * kNb * kNb];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int it0 = A.tile_items[tile], it1 = A.tile_items[tile + 1];
+  if (it0 == it1) return;
+  const double lam = A.ir_lam[tile];
+  if (!(lam >= 0.0)) return;
+  const double2* F = A.ir_fac + (int64_t)tile * solve_factor_elems<R>();
+  for (int k = tid; k < D * LD; k += NT) Mf[k] = F[k];
+  for (int k = tid; k < G::NP * kNb * kNb; k += NT) dinv[k] = F[D * LD + k];
+  cx<T>* slice = A.slices + (int64_t)tile * D;
+  double2 s0 = make_double2(0.0, 0.0), rhs = make_double2(0.0, 0.0);
+  if (tid < D) {
+    s0 = make_double2((double)slice[tid].x, (double)slice[tid].y);
+    double gx = 0.0, gy = 0.0;
+    for (int it = it0; it < it1; ++it) {
+      gx += (double)A.ir_part[(int64_t)it * 2 * D + 2 * tid];
+      gy += (double)A.ir_part[(int64_t)it * 2 * D + 2 * tid + 1];
+    }
+    const cx<T> so = A.ir_old[(int64_t)tile * D + tid];
+    const double ox = A.prox ? (double)so.x : 0.0, oy = A.prox ? (double)so.y : 0.0;
+    rhs = make_double2(gx + lam * (ox - s0.x), gy + lam * (oy - s0.y));
+  }
+  __syncthreads();
+  if (tid >= 64) return;  // one wavefront solves; no barriers below
+  wave_fwd_solve(Mf, dinv, D, LD, rhs, lane);
+  wave_back_solve(Mf, dinv, D, LD, rhs, lane);
+  if (lane < D) slice[lane] = {T(s0.x + rhs.x), T(s0.y + rhs.y)};
 }
 
 template <typename T, int R>
@@ -1455,7 +1487,7 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
       ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
       inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(SolveArgs<T>{
           slices, (const T*)P->partials, C.tile_items, reg, floor_, prox, P->flags, bf16 ? 1 : 0,
-          P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part});
+          P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part, (double2*)P->ir_fac});
     }
     BFC_HIP_TRY(hipGetLastError());
     if constexpr (std::is_same<T, float>::value) {
@@ -1474,9 +1506,9 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
         BFC_HIP_TRY(hipGetLastError());
         {
           ProfScope ps(&P->prof, KIND_INNER_SOLVE, st);
-          inner_solve_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(SolveArgs<T>{
+          inner_refine_kernel<T, R><<<C.nblocks, kSolveThreads, 0, st>>>(SolveArgs<T>{
               slices, (const T*)P->partials, C.tile_items, reg, floor_, prox, P->flags, 2,
-              P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part});
+              P->ir_lam, (cx<T>*)P->ir_old, (const float*)P->ir_part, (double2*)P->ir_fac});
         }
         BFC_HIP_TRY(hipGetLastError());
       }
@@ -2372,7 +2404,7 @@ struct BatchStep {
     sv.push_back(SolveArgs<T>{cores + inner_off(P->n, L, R, p), (const T*)P->partials,
                               C.tile_items, P->cfg.reg_rel, reg_floor_of(P),
                               P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0, P->flags, 0,
-                              nullptr, nullptr, nullptr});
+                              nullptr, nullptr, nullptr, nullptr});
     bs.push_back(C.nblocks);
   }
   static void resid(Problem* P, double* out, std::vector<ResObsArgs<T>>& a,
@@ -2551,6 +2583,19 @@ bfc_status launch_batch(const std::vector<BatchLaunch>& plan, int prec, hipStrea
   for (const BatchLaunch& bl : plan)
     BFC_TRY(prec == BFC_C128 ? launch_batched<double>(bl, st) : launch_batched<float>(bl, st));
   return BFC_OK;
+}
+
+size_t inner_factor_bytes(int r) {
+  switch (r) {
+    case 1: return solve_factor_elems<1>() * 16;
+    case 2: return solve_factor_elems<2>() * 16;
+    case 3: return solve_factor_elems<3>() * 16;
+    case 4: return solve_factor_elems<4>() * 16;
+    case 5: return solve_factor_elems<5>() * 16;
+    case 6: return solve_factor_elems<6>() * 16;
+    case 7: return solve_factor_elems<7>() * 16;
+    default: return solve_factor_elems<8>() * 16;
+  }
 }
 
 size_t inner_partial_bytes(int prec, int r) {
