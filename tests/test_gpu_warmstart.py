@@ -187,3 +187,21 @@ def test_trained_network_beats_the_lowrank_guess():
     summ = ws.summarize(ws.evaluate(net, list(range(900000, 900012)), device=DEV,
                                     starts=("learned", "lowrank")))
     assert summ["learned"]["mean_sweeps_capped"] < summ["lowrank"]["mean_sweeps_capped"], summ
+
+
+def test_layers_without_bias_and_bf16_only_output():
+    m, k, n = 19, 45, 77
+    X, W = _rand((m, k), 21), _rand((k, n), 22, 1 / math.sqrt(k))
+    for act in (0, 1):
+        Y = bfc.mlp_forward(X.to(DEV), W.to(DEV), None, act).cpu().numpy()
+        ref = oracle.mlp.forward(X.numpy(), W.numpy(), None, act)
+        assert np.all(np.abs(Y - ref) <= 1e-5 * _bound(X.numpy(), W.numpy(), None) + 1e-30)
+    Xh, Wh = bfc.mlp_to_bf16(X.to(DEV)), bfc.mlp_to_bf16(W.to(DEV))
+    Yf, _ = bfc.mlp_forward_bf16(Xh, Wh, None, 0, want_f32=True, want_bf16=False)
+    none, Yh = bfc.mlp_forward_bf16(Xh, Wh, None, 0, want_f32=False, want_bf16=True)
+    assert none is None
+    assert np.array_equal(Yh.cpu().numpy().view(np.uint16), oracle.mlp.bf16_bits(Yf.cpu().numpy()))
+    with pytest.raises(bfc.BfcError):
+        bfc.mlp_forward_bf16(Xh, Wh, None, 0, want_f32=False, want_bf16=False)
+    with pytest.raises(bfc.BfcError):
+        bfc.mlp_forward(X.to(DEV), W.to(DEV), None, 2)
