@@ -212,3 +212,26 @@ def test_autotune_restores_cores_and_applies_choice():
             assert np.array_equal(bfc.get_cores(p).cpu().numpy(), bfc.get_cores(q).cpu().numpy())
         for p in probs + fresh:
             p.close()
+
+
+def test_batch_sees_replaced_values(mixed):
+    # bfc_set_values on a batched problem: the batch's next sweep uses the new
+    # values, bit-identically to sweeping that problem alone
+    ws = mixed[:3]
+    probs = [_make(w, "c64") for w in ws]
+    ref = [_make(w, "c64") for w in ws]
+    b = bfc.batch_create(probs)
+    bfc.batch_sweep(b)
+    for p in ref:
+        bfc.sweep(p)
+    new = ws[0].vals * np.exp(0.3j)
+    bfc.set_values(probs[0], new)
+    bfc.set_values(ref[0], new)
+    bfc.batch_sweep(b)
+    for p in ref:
+        bfc.sweep(p)
+    for p, q in zip(probs, ref):
+        assert torch.equal(bfc.get_cores(p), bfc.get_cores(q))
+    b.close()
+    for p in probs + ref:
+        p.close()
