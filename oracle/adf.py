@@ -47,15 +47,7 @@ from .butterfly_als import _blocks_as_core, _core_as_blocks, _n_c, block_keys, d
 
 
 def _qr(M):
-    """Reduced QR of an m x r block.  A leaf block with fewer rows than the
-    rank (c < r) gives Q with c orthonormal columns and r - c zero columns and
-    an r x r R whose last r - c rows are zero, so Q R is still the block and
-    the cores keep their shapes."""
-    m, r = M.shape
     Q, R = np.linalg.qr(M, mode="reduced")
-    if m < r:
-        Q = np.hstack([Q, np.zeros((m, r - m), dtype=Q.dtype)])
-        R = np.vstack([R, np.zeros((r - m, r), dtype=R.dtype)])
     return Q, R
 
 

@@ -90,22 +90,3 @@ def test_adf_sweeps_descend_monotonically():
                                  on_core=lambda p, c: f.append(oracle.objective(c, rows, cols, vals, L)))
     assert all(b <= a * (1 + 1e-12) for a, b in zip(f, f[1:]))
     assert f[-1] < 0.5 * f[0]
-
-
-def test_leaf_blocks_with_fewer_rows_than_the_rank():
-    # c = 2 < r = 3: the padded QR keeps the matrix and the core shapes, and
-    # ADF still descends
-    n, L, r = 16, 3, 3
-    cores = random_cores(n, L, r, seed=4)
-    X = oracle.dense_tensor_network(cores, L)
-    c2 = oracle.orthogonalize_left(cores, 0, L)
-    c3 = oracle.orthogonalize_right(cores, L + 1, L)
-    for c in (c2, c3):
-        assert all(a.shape == b.shape for a, b in zip(c, cores))
-        np.testing.assert_allclose(oracle.dense_tensor_network(c, L), X,
-                                   atol=1e-12 * np.abs(X).max())
-    rows, cols, _, _ = sample_pairs(n, 200, 0, seed=5)
-    vals = green_line_entries(n, 2 * np.pi * 2, rows, cols)
-    f0 = oracle.objective(cores, rows, cols, vals, L)
-    f1 = oracle.objective(oracle.adf_sweep(cores, rows, cols, vals, L), rows, cols, vals, L)
-    assert f1 < f0
