@@ -51,12 +51,22 @@ def _qr(M):
     return Q, R
 
 
+def _require_leaf_rank(c: int, r: int):
+    """App. A.3 replaces every c x r leaf block of Z^1 / Z^(L+2) by the Q of
+    its reduced QR, which has r orthonormal columns only when c >= r.  With
+    fewer rows the step is not defined by the represented matrix (a padded Q
+    depends on the QR's phase convention), so it is rejected."""
+    if c < r:
+        raise ValueError(f"ADF needs r <= c (leaf blocks of c = {c} rows, rank r = {r})")
+
+
 def orthogonalize_left(cores, p: int, L: int):
     """Make core p (0 <= p <= L) left-orthogonal and absorb R into core p+1."""
     cores = [np.array(z, copy=True) for z in cores]
     n, c = _n_c(cores, L)
     r = cores[0].shape[1]
     if p == 0:
+        _require_leaf_rank(c, r)
         for ib in range(2 ** L):
             rows = slice(ib * c, (ib + 1) * c)
             Q, R = _qr(cores[0][rows])
@@ -95,6 +105,7 @@ def orthogonalize_right(cores, p: int, L: int):
     n, c = _n_c(cores, L)
     r = cores[0].shape[1]
     if p == L + 1:
+        _require_leaf_rank(c, r)
         for jb in range(2 ** L):
             rows = slice(jb * c, (jb + 1) * c)
             Q, R = _qr(cores[L + 1][rows])
@@ -156,7 +167,9 @@ def adf_core_step(cores, p: int, rows, cols, vals, L: int):
 def adf_sweep(cores, rows, cols, vals, L: int, on_core=None):
     """One ADF iteration: right-to-left orthogonalization, then cores 0..L+1
     each moved by its line-searched step and left-orthogonalized into the
-    next."""
+    next.  Raises ValueError when the leaf blocks have fewer rows than the
+    rank (c < r)."""
+    _require_leaf_rank(cores[0].shape[0] >> L, cores[0].shape[1])
     cores = right_to_left_sweep(cores, L)
     for p in range(L + 2):
         cores = adf_core_step(cores, p, rows, cols, vals, L)

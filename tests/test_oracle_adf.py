@@ -90,3 +90,22 @@ def test_adf_sweeps_descend_monotonically():
                                  on_core=lambda p, c: f.append(oracle.objective(c, rows, cols, vals, L)))
     assert all(b <= a * (1 + 1e-12) for a, b in zip(f, f[1:]))
     assert f[-1] < 0.5 * f[0]
+
+
+@pytest.mark.parametrize("n,L,r", [(16, 2, 6), (64, 4, 6), (8, 1, 5)])
+def test_leaf_blocks_with_fewer_rows_than_the_rank_are_rejected(n, L, r):
+    # App. A.3 keeps the Q of a reduced QR of every c x r leaf block, which
+    # has r orthonormal columns only when c >= r
+    assert (n >> L) < r
+    cores = _cores(n, L, r, seed=5)
+    rows, cols = np.divmod(np.arange(n * n), n)
+    t = green_line_entries(n, 3.0, rows, cols)
+    with pytest.raises(ValueError, match="r <= c"):
+        oracle.adf_sweep(cores, rows, cols, t, L)
+    with pytest.raises(ValueError, match="r <= c"):
+        oracle.orthogonalize_left(cores, 0, L)
+    with pytest.raises(ValueError, match="r <= c"):
+        oracle.orthogonalize_right(cores, L + 1, L)
+    # the inner steps stack 2r x r slice pairs and stay defined
+    for p in range(1, L + 1):
+        oracle.orthogonalize_left(cores, p, L)

@@ -336,3 +336,131 @@ def test_duplicates_are_separate_rows():
     s_ls, *_ = np.linalg.lstsq(D, t2, rcond=None)
     new = oracle.update_core(cores, 0, rows2, cols2, t2, L, reg_rel=0.0)
     assert np.abs(new[0].ravel() - s_ls).max() <= 1e-10 * np.abs(s_ls).max()
+
+
+# --------------------------------------------------------------------------
+# regularization floor and ladder (Sec. 5.1.1: a regularization keeps the
+# local systems positive definite; its form is the proximal reading).  Every
+# lam below is recomputed from a brute-force design matrix, not read back
+# from the oracle.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("reg_floor", [2.0 ** -20, 1e-3])
+def test_stationarity_with_regularization_floor(p, reg_floor):
+    # lam_B = max(reg_rel, d u) tr(G_B)/d with u = reg_floor: at reg_rel far
+    # below the floor the d u term decides, so a lam missing the factor d
+    # (d = r = 3 or r^2 = 9 here) leaves a gradient of (lam - lam') (s - s_old)
+    n, L, r = 16, 2, 3
+    reg_rel = 1e-14
+    cores, rows, cols, t = _tiny_problem(n, L, r, frac=0.7, seed=11)
+    D = oracle.design_matrix_bruteforce(cores, p, rows, cols, L)
+    new = oracle.update_core(cores, p, rows, cols, t, L, reg_rel=reg_rel, reg_floor=reg_floor)
+    s_new, s_old = new[p].ravel(), cores[p].ravel()
+    checked = 0
+    for lo, hi in _block_columns(p, L, cores[p].shape):
+        DB = D[:, lo:hi]
+        if not np.any(DB != 0):
+            assert np.array_equal(s_new[lo:hi], s_old[lo:hi])
+            continue
+        d = hi - lo
+        G = DB.conj().T @ DB
+        lam = max(reg_rel, d * reg_floor) * np.trace(G).real / d
+        g = DB.conj().T @ (DB @ s_new[lo:hi] - t) + lam * (s_new[lo:hi] - s_old[lo:hi])
+        # the step itself is far above the tolerance, so a wrong lam shows
+        assert lam * np.linalg.norm(s_new[lo:hi] - s_old[lo:hi]) > 1e-9 * np.linalg.norm(DB.conj().T @ t)
+        assert np.linalg.norm(g) <= 1e-11 * np.linalg.norm(DB.conj().T @ t)
+        checked += 1
+    assert checked > 0
+
+
+def _one_block_problem(r=3, seed=21, skew=1.0):
+    # every observed entry in row 0: core 0 has exactly one non-empty block.
+    # skew scales row 0 of every slice of Z^2, hence component 0 of every
+    # design row (the right environment), so that G[0][0] is skew^2 times the
+    # other diagonal entries: lam = x tau is then resolvable at the small
+    # entries down to x ~ 1e-16 / skew^2
+    n, L = 16, 2
+    cores = _cores(n, L, r, seed)
+    cores[1] = cores[1].copy()
+    cores[1][:, 0, :] *= skew
+    cols = np.arange(n)
+    rows = np.zeros(n, dtype=np.int64)
+    t = green_line_entries(n, 3.0, rows, cols)
+    D = oracle.design_matrix_bruteforce(cores, 0, rows, cols, L)[:, :r]
+    return cores, rows, cols, t, L, D.conj().T @ D
+
+
+class _FailingCholesky:
+    """Stands in for scipy.linalg.cho_factor: fails the first `fails` calls
+    and records the diagonal of every matrix it is given."""
+
+    def __init__(self, real, fails):
+        self.real, self.fails, self.diags = real, fails, []
+
+    def __call__(self, M, *args, **kw):
+        self.diags.append(np.real(np.diag(M)).copy())
+        if len(self.diags) <= self.fails:
+            raise np.linalg.LinAlgError("forced failure")
+        return self.real(M, *args, **kw)
+
+
+@pytest.mark.parametrize("reg_rel,reg_floor", [
+    (1e-3, 0.0),       # lam0 well above d u tau: each rung is 100 lam
+    (1e-30, 0.0),      # lam0 tiny: the first rung jumps to d 2^-53 tau
+    (0.0, 2.0 ** -20),  # floor only: lam0 = d u tau, then 100 lam
+    (1e-30, 1e-9),     # floor u = 1e-9 sets lam0 = d u tau
+])
+@pytest.mark.parametrize("fails", [1, 2, 3])
+def test_regularization_ladder_rungs(monkeypatch, reg_rel, reg_floor, fails):
+    import scipy.linalg
+
+    r = 3
+    cores, rows, cols, t, L, G = _one_block_problem(r, skew=1e4)
+    gd = np.real(np.diag(G))
+    k = int(np.argmin(gd))
+    assert gd[k] < 1e-6 * gd.max()
+    fake = _FailingCholesky(scipy.linalg.cho_factor, fails)
+    monkeypatch.setattr(scipy.linalg, "cho_factor", fake)
+    new = oracle.update_core(cores, 0, rows, cols, t, L, reg_rel=reg_rel, reg_floor=reg_floor)
+    d = r
+    tau = np.trace(G).real / d
+    unit = max(reg_floor, 2.0 ** -53)
+    lam = max(reg_rel, d * reg_floor) * tau
+    want = [lam]
+    for _ in range(fails):
+        lam = max(100.0 * lam, d * unit * tau)
+        want.append(lam)
+    # lam from the smallest diagonal entry, where the subtraction is exact
+    # to a few units of that entry
+    got = [float(dg[k] - gd[k]) for dg in fake.diags]
+    assert len(got) == fails + 1
+    for g_, w_ in zip(got, want):
+        assert g_ == pytest.approx(w_, rel=1e-3, abs=64 * 2.0 ** -53 * gd[k])
+    # the accepted rung's solution: (G + lam I) s = h + lam s_old
+    A = oracle.design_matrix_bruteforce(cores, 0, rows, cols, L)[:, :r]
+    s = np.linalg.solve(G + want[-1] * np.eye(d), A.conj().T @ t + want[-1] * cores[0][0])
+    assert np.abs(new[0][0] - s).max() <= 1e-6 * np.abs(s).max()
+
+
+def test_regularization_ladder_gives_up_after_three_rungs(monkeypatch):
+    import scipy.linalg
+
+    cores, rows, cols, t, L, G = _one_block_problem()
+    fake = _FailingCholesky(scipy.linalg.cho_factor, 4)
+    monkeypatch.setattr(scipy.linalg, "cho_factor", fake)
+    with pytest.raises(oracle.OracleNotSPD):
+        oracle.update_core(cores, 0, rows, cols, t, L, reg_rel=1e-3)
+    assert len(fake.diags) == 4
+
+
+def test_no_ladder_without_regularization(monkeypatch):
+    # lam = 0 (no reg_rel, no floor): a failed factorization is final
+    import scipy.linalg
+
+    cores, rows, cols, t, L, G = _one_block_problem()
+    fake = _FailingCholesky(scipy.linalg.cho_factor, 1)
+    monkeypatch.setattr(scipy.linalg, "cho_factor", fake)
+    with pytest.raises(oracle.OracleNotSPD):
+        oracle.update_core(cores, 0, rows, cols, t, L, reg_rel=0.0)
+    assert len(fake.diags) == 1
