@@ -28,7 +28,9 @@
  * the observed entries it touches,
  *     (K + lam I) s = y + lam s_old        (proximal, default)
  *     (K + lam I) s = y                    (ridge)
- * with K = sum conj(a) a^T, y = sum conj(a) t, lam = reg_rel * trace(K) / d.
+ * with K = sum conj(a) a^T, y = sum conj(a) t and
+ * lam = max(reg_rel, d * u) * trace(K) / d, u the rounding level described
+ * at bfc_init_cores (the regularization floor).
  * A fiber or slice with no observed entry keeps its values.  Inner-core
  * slices are stored row-major: s[a*r + b] = Z[k][a][b].
  *
@@ -75,7 +77,11 @@ typedef int32_t bfc_status;
 #define BFC_C128 0        /* complex128 cores and contractions, FP64 Gram, FP64 solves        */
 #define BFC_C64 1         /* complex64 cores and contractions, FP32 Gram, FP64 solves          */
 #define BFC_C64_BF16GRAM 2 /* as BFC_C64 but the inner cores' Gram/right-hand-side products
-                             take bf16 inputs (FP32 accumulation); each inner FP64 solve is
+                             take bf16 inputs (FP32 accumulation on the BF16 matrix cores):
+                             every FP32 row value x is split as x = h + m + l with h, m, l
+                             bf16 (h = bf16(x), m = bf16(x - h), l = bf16(x - h - m)) and the
+                             products h h' + h m' + m h' + h l' + m m' + l h' are summed, so
+                             the Gram keeps FP32-level accuracy; each inner FP64 solve is
                              followed by one refinement step whose residual
                              sum conj(a_e)(t_e - a_e.s) is recomputed from the entries in
                              FP32, solved with the same factor and regularization (the outer
@@ -94,8 +100,12 @@ typedef struct bfc_config {
     int32_t r;          /* rank, 1 <= r <= BFC_MAX_RANK                              */
     int32_t precision;  /* BFC_C128, BFC_C64 or BFC_C64_BF16GRAM                     */
     int32_t reg_mode;   /* BFC_REG_PROXIMAL or BFC_REG_RIDGE                         */
-    double reg_rel;     /* lam = reg_rel * trace(K)/d; >= 0                           */
+    double reg_rel;     /* relative regularization, >= 0: lam = max(reg_rel, d u) trace(K)/d */
     uint64_t seed;      /* random start when bfc_init_cores gets no initial cores    */
+    double reg_floor;   /* lower bound on u, in [0, 2^-4]; 0 keeps the mode's own u_K.
+                           An FP64 run with reg_floor = 2^-20 uses exactly the
+                           regularization of the complex64 modes, so the two
+                           differ only in their arithmetic                           */
 } bfc_config;
 
 typedef struct bfc_problem bfc_problem;
@@ -114,13 +124,14 @@ int64_t bfc_num_params(int64_t n, int32_t L, int32_t r);
  * a counter-based generator keyed by cfg->seed.
  *
  * Regularization used by every later core update: with tau = trace(K)/d,
- * lam = max(reg_rel, d * u_K) * tau where u_K is the unit roundoff of the
- * Gram accumulation (0 in BFC_C128; 2^-20 for the FP32-accumulated Grams of
- * the complex64 modes: the FP32 unit roundoff 2^-24 times the sqrt(256)
- * growth of the sums forming them; 2^-10 for the inner Grams of
- * BFC_C64_BF16GRAM), so that rounding cannot make K + lam I indefinite.  If the FP64 Cholesky
- * factorization still fails while lam > 0, lam is raised to
- * max(100 lam, d max(u_K, 2^-53) tau), at most three times.
+ * lam = max(reg_rel, d * u) * tau, u = max(u_K, cfg->reg_floor), where u_K
+ * is the rounding level of the Gram accumulation (0 in BFC_C128; 2^-20 for
+ * the FP32-accumulated Grams of the complex64 modes: the FP32 unit roundoff
+ * 2^-24 times the sqrt(256) growth of the sums forming them; the same 2^-20
+ * for the inner Grams of BFC_C64_BF16GRAM, whose bf16 inputs are split in
+ * three bf16 parts), so that rounding cannot make K + lam I indefinite.  If
+ * the FP64 Cholesky factorization still fails while lam > 0, lam is raised to
+ * max(100 lam, d max(u, 2^-53) tau), at most three times.
  * Returns EINVAL for nnz < 1, a bad config (n not c*2^L, r or L out of
  * range, negative reg_rel) or an index outside [0, n); ENONFINITE for a
  * non-finite value; ENOMEM when device memory runs out.  On success *out

@@ -81,6 +81,7 @@ class BfcConfig(ctypes.Structure):
         ("reg_mode", ctypes.c_int32),
         ("reg_rel", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("reg_floor", ctypes.c_double),
     ]
 
 

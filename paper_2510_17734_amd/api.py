@@ -87,10 +87,12 @@ class Config:
     reg_mode: str = "proximal"
     reg_rel: float = 1e-10
     seed: int = 0
+    reg_floor: float = 0.0
 
     def to_c(self) -> _lib.BfcConfig:
         return _lib.BfcConfig(self.n, self.L, self.r, PRECISIONS[self.precision],
-                              REG_MODES[self.reg_mode], float(self.reg_rel), int(self.seed))
+                              REG_MODES[self.reg_mode], float(self.reg_rel), int(self.seed),
+                              float(self.reg_floor))
 
 
 class Problem:

@@ -120,6 +120,10 @@ static bfc_status check_config(const bfc_config* cfg, int32_t* c_out) {
     set_error("reg_rel must be >= 0");
     return BFC_EINVAL;
   }
+  if (!(cfg->reg_floor >= 0.0 && cfg->reg_floor <= 0x1p-4)) {
+    set_error("reg_floor must be in [0, 2^-4]");
+    return BFC_EINVAL;
+  }
   *c_out = (int32_t)(cfg->n / two_l);
   return BFC_OK;
 }

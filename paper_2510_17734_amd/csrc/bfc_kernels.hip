@@ -606,22 +606,22 @@ __global__ __launch_bounds__(64) void inner_gram_kernel_batched(const GramArgs<T
 }
 
 
-// BF16-input variant (precision BFC_C64_BF16GRAM): the same A/B rows are
-// rounded to bfloat16 and multiplied by the 16x16x32 BF16 MFMA with FP32
-// accumulation.  The rows are staged transposed (coordinate-major, one
-// column per subgroup), so each lane reads its eight consecutive subgroups of
-// one coordinate as one 16-byte vector: lane l holds A[l%16][8(l/16)+t],
-// the layout of the instruction's A and B operands.  The output layout equals
-// the FP32 instruction's, so the partial products keep their format.
+// BF16-input variant (precision BFC_C64_BF16GRAM): the same A/B rows as the
+// FP32 kernel, multiplied on the BF16 matrix cores (16x16x32, FP32
+// accumulation).  Each FP32 value x is split into three bf16 parts
+// h = bf16(x), m = bf16(x - h), l = bf16(x - h - m) (round to nearest even;
+// both differences are exact in FP32), so x = h + m + l to about 2^-27 of |x|,
+// and the six products h h' + h m' + m h' + h l' + m m' + l h' give x x' to
+// about 2^-26 relative (the dropped m l', l m', l l' are smaller): each
+// product of two bf16 values is exact in FP32, so the Gram carries the
+// rounding of its FP32 accumulation, as in the FP32 kernel, and takes the same
+// regularization floor.  Rows are staged as FP32 values, coordinate-major, in
+// two phases of 32 subgroups (one 32-deep k block of the instruction each):
+// lane l reads the eight consecutive subgroups 8(l/16)..8(l/16)+7 of
+// coordinate l%16 of a tile as two 16-byte loads and splits them in
+// registers.  The output layout equals the FP32 instruction's, so the partial
+// products keep their format.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-// BF16-Gram mode: regularization floor of the inner solves and refinement
-// steps.  A bf16-formed Gram differs from the exact one by up to ~2^-8 of its
-// entries; refinement with that factor contracts only where lam dominates the
-// difference, and where it does not, it amplifies the error (more steps make
-// it worse).  Measured on the Green's-function workloads: at 2^-12 single
-// updates can raise the objective (train error +25% in one sweep), at 2^-10
-// every sweep descends, at 2^-8 too but the damping slows convergence.
-constexpr double kBf16RegFloor = 0x1p-10;
 // Regularization floor of the FP32-accumulated Grams: the FP32 unit roundoff
 // 2^-24 times the sqrt(256) growth of the sums that form them (at most 8
 // entries per subgroup, then up to 128 subgroups per MFMA chain and per
@@ -630,7 +630,32 @@ constexpr double kBf16RegFloor = 0x1p-10;
 // sweeps on the Green's-function workloads); at 2^-20 they stay bounded.
 constexpr double kF32RegFloor = 0x1p-20;
 constexpr int kBf16IrSteps = 1;
-constexpr int kBfLd = 64 + 8;  // subgroups per staged coordinate row, padded
+constexpr int kBfLdk = 32 + 4;  // subgroups per staged coordinate row (one phase), padded
+
+// Rounding level u of a problem's regularization floor: that of its Gram
+// accumulation, raised to the configured lower bound.
+inline double reg_floor_of(const Problem* P) {
+  const double uk = P->prec == BFC_C128 ? 0.0 : kF32RegFloor;
+  return uk > P->cfg.reg_floor ? uk : P->cfg.reg_floor;
+}
+
+// x = h + m + l, each part bf16 rounded to nearest even (see above).
+__device__ __attribute__((always_inline)) inline void split_bf16x3(const floatx4& x0,
+                                                                   const floatx4& x1,
+                                                                   bf16x8& h, bf16x8& m,
+                                                                   bf16x8& l) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const float x = t < 4 ? x0[t] : x1[t - 4];
+    const __bf16 hh = (__bf16)x;
+    const float r1 = x - (float)hh;
+    const __bf16 mm = (__bf16)r1;
+    const float r2 = r1 - (float)mm;
+    h[t] = hh;
+    m[t] = mm;
+    l[t] = (__bf16)r2;
+  }
+}
 
 template <int R, int BYROW>
 __global__ __launch_bounds__(64) void inner_gram_bf16_kernel(
@@ -638,8 +663,8 @@ __global__ __launch_bounds__(64) void inner_gram_bf16_kernel(
     const cx<float>* vals, const int32_t* sub_off, const WorkItem* items, float* partials) {
   typedef InnerGeom<R> G;
   typedef Mfma<float>::acc_t acc_t;
-  __shared__ __attribute__((aligned(16))) __bf16 At[G::WP * kBfLd];
-  __shared__ __attribute__((aligned(16))) __bf16 Bt[G::WP * kBfLd];
+  __shared__ __attribute__((aligned(16))) float At[G::WP * kBfLdk];
+  __shared__ __attribute__((aligned(16))) float Bt[G::WP * kBfLdk];
   const int lane = threadIdx.x;
   const int item = xcd_swizzle(blockIdx.x, gridDim.x);
   const WorkItem it = items[item];
@@ -660,31 +685,47 @@ __global__ __launch_bounds__(64) void inner_gram_bf16_kernel(
     float a[G::W], b[G::W];
     subgroup_rows<float, R, BYROW>(live, e0, e1, lenv, lidx, renv, ridx, vals, a, b);
 #pragma unroll
-    for (int k = 0; k < G::W; ++k) {
-      At[k * kBfLd + lane] = (__bf16)a[k];
-      Bt[k * kBfLd + lane] = (__bf16)b[k];
+    for (int ph = 0; ph < 2; ++ph) {
+      if ((lane >> 5) == ph) {
+        const int col = lane & 31;
+#pragma unroll
+        for (int k = 0; k < G::W; ++k) {
+          At[k * kBfLdk + col] = a[k];
+          Bt[k * kBfLdk + col] = b[k];
+        }
+#pragma unroll
+        for (int k = G::W; k < G::WP; ++k) {
+          At[k * kBfLdk + col] = 0.f;
+          Bt[k * kBfLdk + col] = 0.f;
+        }
+      }
+      __syncthreads();
+      const int off = (lane & 15) * kBfLdk + 8 * (lane >> 4);
+      bf16x8 yh[G::NB], ym[G::NB], yl[G::NB];
+#pragma unroll
+      for (int y = 0; y < G::NB; ++y) {
+        const float* src = Bt + y * 16 * kBfLdk + off;
+        split_bf16x3(*(const floatx4*)src, *(const floatx4*)(src + 4), yh[y], ym[y], yl[y]);
+      }
+#pragma unroll
+      for (int x = 0; x < G::NB; ++x) {
+        const float* src = At + x * 16 * kBfLdk + off;
+        bf16x8 xh, xm, xl;
+        split_bf16x3(*(const floatx4*)src, *(const floatx4*)(src + 4), xh, xm, xl);
+#pragma unroll
+        for (int y = 0; y < G::NB; ++y) {
+          // the small products first
+          acc_t c = acc[x][y];
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh[y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, ym[y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl[y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, yh[y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ym[y], c, 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yh[y], c, 0, 0, 0);
+        }
+      }
+      __syncthreads();
     }
-#pragma unroll
-    for (int k = G::W; k < G::WP; ++k) {
-      At[k * kBfLd + lane] = (__bf16)0.f;
-      Bt[k * kBfLd + lane] = (__bf16)0.f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
-      const int off = (lane & 15) * kBfLd + kb * 32 + 8 * (lane >> 4);
-      bf16x8 xa[G::NB], yb[G::NB];
-#pragma unroll
-      for (int x = 0; x < G::NB; ++x) xa[x] = *(const bf16x8*)(At + x * 16 * kBfLd + off);
-#pragma unroll
-      for (int y = 0; y < G::NB; ++y) yb[y] = *(const bf16x8*)(Bt + y * 16 * kBfLd + off);
-#pragma unroll
-      for (int x = 0; x < G::NB; ++x)
-#pragma unroll
-        for (int y = 0; y < G::NB; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[x], yb[y], acc[x][y], 0, 0, 0);
-    }
-    __syncthreads();
   }
   float* out = partials + (int64_t)item * G::WP * G::WP;
 #pragma unroll
@@ -1427,10 +1468,7 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   // keep lam above the rounding level of the Gram: none for FP64, the unit
   // roundoff of FP32 accumulation, or that of the bf16 inputs
   const int L = P->L;
-  const bool outer = p == 0 || p == L + 1;  // outer Grams are FP32 in both complex64 modes
-  const double floor_ = P->prec == BFC_C128             ? 0.0
-                        : (P->prec == BFC_C64 || outer) ? kF32RegFloor
-                                                        : kBf16RegFloor;
+  const double floor_ = reg_floor_of(P);
   const int prox = P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0;
   {
     ProfScope ps(&P->prof, KIND_ENV, st);
@@ -2345,8 +2383,6 @@ bfc_status upload_tasks(Batch* B, int kind, int r, const std::vector<A>& args,
       .push_back(bl);
   return BFC_OK;
 }
-
-inline double reg_floor_of(const Problem* P) { return P->prec == BFC_C128 ? 0.0 : kF32RegFloor; }
 
 template <typename T, int R>
 struct BatchStep {

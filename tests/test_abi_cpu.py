@@ -30,9 +30,11 @@ def test_library_exports_every_symbol():
 
 
 def test_config_struct_layout():
-    # int64 n, int32 L, r, precision, reg_mode, double reg_rel, uint64 seed
-    assert ctypes.sizeof(_lib.BfcConfig) == 40
+    # int64 n, int32 L, r, precision, reg_mode, double reg_rel, uint64 seed,
+    # double reg_floor
+    assert ctypes.sizeof(_lib.BfcConfig) == 48
     assert _lib.BfcConfig.reg_rel.offset == 24
+    assert _lib.BfcConfig.reg_floor.offset == 40
 
 
 def test_num_params():
@@ -58,6 +60,8 @@ def _init(cfg, nnz=10, rows=1, cols=1, vals=1):
     (_lib.BfcConfig(256, -1, 4, 0, 0, 1e-10, 0), "L"),
     (_lib.BfcConfig(256, 4, 4, 7, 0, 1e-10, 0), "precision"),
     (_lib.BfcConfig(256, 4, 4, 0, 3, 1e-10, 0), "regularization"),
+    (_lib.BfcConfig(256, 4, 4, 0, 0, 1e-10, 0, -1.0), "reg_floor"),
+    (_lib.BfcConfig(256, 4, 4, 0, 0, 1e-10, 0, 0.5), "reg_floor"),
     (_lib.BfcConfig(256, 4, 4, 0, 0, -1.0, 0), "reg_rel"),
 ])
 def test_init_rejects_bad_config(cfg, why):
@@ -104,3 +108,4 @@ def test_item_size_argument_checks():
     chosen = ctypes.c_int32()
     assert lib.bfc_autotune_item_size(None, 1, 1, None, 0, ctypes.byref(chosen), None,
                                       None) == _lib.BFC_EINVAL
+

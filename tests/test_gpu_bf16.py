@@ -1,19 +1,19 @@
 """GPU parity of the BF16-Gram mode (precision "bf16gram") against the oracle.
 
-In this mode the inner cores' Gram / right-hand-side products take bf16
-inputs (FP32 accumulation), and each inner FP64 solve is followed by one
-refinement step whose residual sum conj(a_e)(t_e - a_e . s) is recomputed from
-the entries in FP32.  The regularization floor of the inner solves is 2^-10
-(the outer cores keep the FP32 floor 2^-20), so the oracle is run with the
-same floors and each update is judged against the regularized FP64 optimum.
+In this mode the inner cores' Gram / right-hand-side products run on the BF16
+matrix cores with FP32 accumulation: every FP32 row value is split into three
+bf16 parts (x = h + m + l to about 2^-27 of |x|) and six of the nine part
+products are summed (the dropped ones are below 2^-26 relative), so the Gram
+carries the rounding of its FP32 accumulation, as in the complex64 mode.
+Each inner FP64 solve is followed by one refinement step whose residual
+sum conj(a_e)(t_e - a_e . s) is recomputed from the entries in FP32.  The
+regularization floor is the complex64 modes' 2^-20 for every core, so the
+oracle is run with that floor and each update is judged against the
+regularized FP64 optimum.
 
-Tolerances: bf16 rounds the Gram's inputs to 8 significant bits, so the
-factor differs from the exact Gram by ~2^-8 of its entries; one refinement
-step contracts that error by about ||(K_bf + lam I)^-1 (K - K_bf)||, which the
-floor keeps below one but not far below it on ill-conditioned slices.
-Measured on these shapes: block objectives within 8e-3 of the regularized
-optimum over six sweeps; the bar is 3e-2.  The sweep must never raise the
-objective (it stays a descent method).
+Tolerances: as in the complex64 parity tests, a core update's block
+objective must be within 1e-4 relative of the FP64 optimum, and the sweep
+must never raise the objective (it stays a descent method).
 """
 import math
 
@@ -28,7 +28,6 @@ from workloads import make_workload, random_cores, sample_pairs, green_line_entr
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-BF16_FLOOR = 2.0 ** -10
 F32_FLOOR = 2.0 ** -20
 SHAPES = [(256, 4, 4, 8155), (128, 4, 5, 4000), (128, 3, 8, 6000), (96, 3, 3, 2500),
           (64, 2, 6, 3000)]
@@ -64,14 +63,12 @@ def test_bf16_core_updates_near_regularized_optimum(shape):
             bfc.sweep_core(prob, p)
             bfc.sync_status(prob)
             after = _gpu_cores(prob)
-            floor = F32_FLOOR if p in (0, L + 1) else BF16_FLOOR
             ref = oracle.update_core(before, p, rows, cols, vals, L, reg_rel=1e-10,
-                                     reg_floor=floor)
+                                     reg_floor=F32_FLOOR)
             f_ref = oracle.objective(ref, rows, cols, vals, L)
             f_gpu = oracle.objective(after, rows, cols, vals, L)
             f_before = oracle.objective(before, rows, cols, vals, L)
-            tol = 1e-4 if p in (0, L + 1) else 3e-2
-            assert f_gpu <= f_ref * (1 + tol) + 1e-12 * f_before, (sweep, p, f_gpu, f_ref)
+            assert f_gpu <= f_ref * (1 + 1e-4) + 1e-12 * f_before, (sweep, p, f_gpu, f_ref)
             assert f_gpu <= f_before * (1 + 1e-6), (sweep, p, f_gpu, f_before)
             for q in range(L + 2):
                 if q != p:
@@ -79,10 +76,10 @@ def test_bf16_core_updates_near_regularized_optimum(shape):
     prob.close()
 
 
-def test_bf16_refinement_beats_the_bf16_factor_alone():
-    # the refined update is closer to the regularized optimum than a solve
-    # with a bf16-rounded Gram can be: compare with the oracle's update from
-    # bf16-rounded design rows (the error one unrefined solve would carry)
+def test_bf16_split_beats_a_one_part_bf16_gram():
+    # the update is far closer to the regularized optimum than a solve with
+    # a Gram of one-part bf16-rounded design rows can be (the error such a
+    # solve carries even before any refinement)
     n, L, r, nnz = 128, 4, 5, 4000
     rows, cols, vals, cores0 = _custom(n, L, r, nnz, seed=11)
     prob = _problem(n, L, r, rows, cols, vals, cores0)
@@ -93,7 +90,7 @@ def test_bf16_refinement_beats_the_bf16_factor_alone():
     p = 2
     bfc.sweep_core(prob, p)
     after = _gpu_cores(prob)
-    ref = oracle.update_core(before, p, rows, cols, vals, L, reg_rel=1e-10, reg_floor=BF16_FLOOR)
+    ref = oracle.update_core(before, p, rows, cols, vals, L, reg_rel=1e-10, reg_floor=F32_FLOOR)
 
     def bf16(x):
         # round-to-nearest-even to 8 significant bits, componentwise
@@ -114,13 +111,13 @@ def test_bf16_refinement_beats_the_bf16_factor_alone():
         a = np.einsum("ea,eb->eab", bf16(lrows[sel]), bf16(rrows[sel])).reshape(sel.sum(), r * r)
         K = a.conj().T @ a
         h = a.conj().T @ vals[sel]
-        lam = max(1e-10, r * r * BF16_FLOOR) * np.trace(K).real / (r * r)
+        lam = max(1e-10, r * r * F32_FLOOR) * np.trace(K).real / (r * r)
         s_old = before[p][k].reshape(-1)
         s = np.linalg.solve(K + lam * np.eye(r * r), h + lam * s_old)
         nref = np.linalg.norm(ref[p][k])
         err_plain.append(np.linalg.norm(s - ref[p][k].reshape(-1)) / nref)
         err_gpu.append(np.linalg.norm(after[p][k] - ref[p][k]) / nref)
-    assert np.median(err_gpu) < np.median(err_plain), (np.median(err_gpu), np.median(err_plain))
+    assert np.median(err_gpu) < 1e-2 * np.median(err_plain), (np.median(err_gpu), np.median(err_plain))
     prob.close()
 
 

@@ -30,11 +30,12 @@ def _gpu_cores(prob, w):
     return bfc.unflatten_cores(bfc.get_cores(prob).cpu().numpy(), w.n, w.L, w.r)
 
 
-FLOORS = {"c128": 0.0, "c64": 2.0 ** -20, "bf16gram": 2.0 ** -10}
+FLOORS = {"c128": 0.0, "c64": 2.0 ** -20, "bf16gram": 2.0 ** -20}
 
 
-def _sampled_check(w, precision, sweeps_before=0, cores=None):
-    cfg = bfc.Config(n=w.n, L=w.L, r=w.r, precision=precision, reg_rel=1e-10)
+def _sampled_check(w, precision, sweeps_before=0, cores=None, reg_floor=0.0):
+    cfg = bfc.Config(n=w.n, L=w.L, r=w.r, precision=precision, reg_rel=1e-10,
+                     reg_floor=reg_floor)
     prob = bfc.init_cores(cfg, w.rows, w.cols, w.vals, w.cores0, device=DEV)
     for _ in range(sweeps_before):
         bfc.sweep(prob)
@@ -52,8 +53,7 @@ def _sampled_check(w, precision, sweeps_before=0, cores=None):
         counts = np.bincount(keys[p], minlength=nb)
         pick[0] = int(np.argmax(counts))
         sel = np.isin(keys[p], pick)
-        outer = p in (0, w.L + 1)
-        floor = FLOORS["c64"] if (outer and precision == "bf16gram") else FLOORS[precision]
+        floor = max(FLOORS[precision], reg_floor)
         ref = oracle.update_core(before, p, w.rows[sel], w.cols[sel], w.vals[sel], w.L,
                                  reg_rel=1e-10, reg_floor=floor)
         if precision == "c128":
@@ -62,11 +62,10 @@ def _sampled_check(w, precision, sweeps_before=0, cores=None):
             assert err <= 1e-9, (p, err)
         else:
             # block objective of the GPU update against the FP64 optimum: within
-            # 1e-4 relative plus 1e-6 of the blocks' data energy (an FP32 Gram
-            # perturbs the solution by about cond(K) * sqrt(m) * 2^-24); the
-            # BF16-Gram inner updates within 3e-2 (one refinement step, see
-            # test_gpu_bf16)
-            tol = 3e-2 if (precision == "bf16gram" and not outer) else 1e-4
+            # 1e-4 relative plus 1e-6 of the blocks' data energy (an FP32 Gram,
+            # or the three-part bf16 one, perturbs the solution by about
+            # cond(K) * sqrt(m) * 2^-24)
+            tol = 1e-4
             mixed = list(before)
             mixed[p] = ref[p].copy()
             f_ref = oracle.objective(mixed, w.rows[sel], w.cols[sel], w.vals[sel], w.L)
@@ -121,6 +120,12 @@ def test_fullsize_planes_c64_sampled(planes):
 
 def test_fullsize_planes_bf16gram_sampled(planes):
     _sampled_check(planes, "bf16gram")
+
+
+def test_fullsize_planes_c128_sampled(planes):
+    # the FP64 reference of this workload, with the complex64 modes'
+    # regularization floor (the oracle takes the same floor)
+    _sampled_check(planes, "c128", reg_floor=2.0 ** -20)
 
 
 def test_fullsize_planes_residual(planes):
