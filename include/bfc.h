@@ -405,6 +405,27 @@ bfc_status bfc_lowrank_to_butterfly(int64_t n, int32_t L, int32_t r, int32_t R, 
                                     const void* d_A, const void* d_B, const void* d_sketches,
                                     void* d_cores_out, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * conversion as bfc_lowrank_to_butterfly, with the same arguments, checks and
+ * results (bit-identical: the same kernels in the same order), but it calls
+ * no hipMalloc, hipFree or other allocating routine and does not synchronize:
+ * the work is only enqueued on hip_stream.  Its scratch is a fixed 16 MiB
+ * device array per GPU (held from the first call on that GPU until the
+ * process ends), so it accepts only sizes with
+ * 16 * 2^L (4 r R + R (r + p)) <= 16 MiB (e.g. L <= 11 at r = R = 8, p = 4);
+ * larger sizes return BFC_EINVAL with a message naming the limit.  Every
+ * call on one GPU shares that array, which keeps the last call's values (the
+ * conversion writes every scratch value before reading it, so nothing needs
+ * clearing): calls that overlap on one GPU (other streams, other threads)
+ * race and must be ordered by the caller.
+ */
+bfc_status bfc_lowrank_to_butterfly_noalloc(int64_t n, int32_t L, int32_t r, int32_t R, int32_t p,
+                                            const void* d_A, const void* d_B,
+                                            const void* d_sketches, void* d_cores_out,
+                                            void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

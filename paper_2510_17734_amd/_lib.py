@@ -55,6 +55,7 @@ EXPORTS = (
     "bfc_set_item_size",
     "bfc_autotune_item_size",
     "bfc_lowrank_to_butterfly",
+    "bfc_lowrank_to_butterfly_noalloc",
     "bfc_adam_sweep",
     "bfc_adam_reset",
     "bfc_adf_sweep",
@@ -150,6 +151,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_autotune_item_size.restype = i32
     lib.bfc_lowrank_to_butterfly.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.bfc_lowrank_to_butterfly.restype = i32
+    lib.bfc_lowrank_to_butterfly_noalloc.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.bfc_lowrank_to_butterfly_noalloc.restype = i32
     d = ctypes.c_double
     lib.bfc_adam_sweep.argtypes = [P, i32, d, d, d, d, vp]
     lib.bfc_adam_sweep.restype = i32

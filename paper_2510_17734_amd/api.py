@@ -331,11 +331,14 @@ def autotune_item_size(problems, sweeps: int = 2, candidates=(64, 128, 256, 512)
 
 
 def lowrank_to_butterfly(A, B, L: int, r: int, p: int, sketches, *, device="cuda:0",
-                         stream=None) -> torch.Tensor:
+                         stream=None, noalloc: bool = False, out=None) -> torch.Tensor:
     """bfc_lowrank_to_butterfly: butterfly cores (ABI layout, complex128 on the
     device) from the factors A, B (n x R) of X = A B^T.  ``sketches`` are the
     Gaussian matrices the algorithm draws (row-side levels, then column-side
-    levels), as arrays or tensors, or one flat complex128 tensor."""
+    levels), as arrays or tensors, or one flat complex128 tensor.
+    ``noalloc``: call bfc_lowrank_to_butterfly_noalloc instead (the library
+    allocates nothing and only enqueues the work on the stream); ``out``: a
+    complex128 device tensor of bfc_num_params values to write into."""
     device = torch.device(device)
     A_t = _dev_c128(A, device)
     B_t = _dev_c128(B, device)
@@ -352,10 +355,16 @@ def lowrank_to_butterfly(A, B, L: int, r: int, p: int, sketches, *, device="cuda
     if L >= 1 and sk.numel() != need:
         raise ValueError(f"expected {need} sketch values, got {sk.numel()}")
     lib = _lib.load()
-    out = torch.empty(int(lib.bfc_num_params(n, L, r)), dtype=torch.complex128, device=device)
-    _check(lib.bfc_lowrank_to_butterfly(n, int(L), int(r), R, int(p), _ptr(A_t), _ptr(B_t),
-                                        _ptr(sk), _ptr(out), _stream(stream)),
-           "bfc_lowrank_to_butterfly")
+    m = int(lib.bfc_num_params(n, L, r))
+    if out is None:
+        out = torch.empty(m, dtype=torch.complex128, device=device)
+    elif (out.dtype != torch.complex128 or out.numel() != m or not out.is_contiguous()
+          or out.device != device):
+        raise ValueError(f"out must be a contiguous complex128 tensor of {m} values on {device}")
+    fn = lib.bfc_lowrank_to_butterfly_noalloc if noalloc else lib.bfc_lowrank_to_butterfly
+    _check(fn(n, int(L), int(r), R, int(p), _ptr(A_t), _ptr(B_t), _ptr(sk), _ptr(out),
+              _stream(stream)),
+           "bfc_lowrank_to_butterfly_noalloc" if noalloc else "bfc_lowrank_to_butterfly")
     return out
 
 

@@ -16,6 +16,10 @@
 // sketch (at most 64 rows: c <= 64 at the leaves, 2r at inner levels) and
 // its r + p columns in registers; column norms and inner products are
 // wavefront butterfly sums, identical in every lane.
+#include <mutex>
+#include <string>
+#include <utility>
+
 #include "bfc_common.h"
 #include "bfc_device.h"
 
@@ -287,37 +291,46 @@ __global__ __launch_bounds__(256) void lr_middle_kernel(double2* core, const dou
 
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-}  // namespace
-}  // namespace bfc
-
-using namespace bfc;
-
-extern "C" bfc_status bfc_lowrank_to_butterfly(int64_t n, int32_t L, int32_t r, int32_t R,
-                                               int32_t p, const void* d_A, const void* d_B,
-                                               const void* d_sketches, void* d_cores_out,
-                                               void* hip_stream) {
-  set_error("");
+// Arguments shared by both entry points, checked; sets the error message.
+bfc_status lr2bf_check(int64_t n, int32_t L, int32_t r, int32_t R, int32_t p, const void* d_A,
+                       const void* d_B, const void* d_sketches, const void* d_cores_out,
+                       const char* who) {
   if (!d_A || !d_B || !d_sketches || !d_cores_out) {
-    set_error("bfc_lowrank_to_butterfly: null pointer");
+    set_error(std::string(who) + ": null pointer");
     return BFC_EINVAL;
   }
   if (L < 1 || L > 24 || n <= 0 || (n >> L) << L != n) {
-    set_error("bfc_lowrank_to_butterfly: need L >= 1 and n = c 2^L");
+    set_error(std::string(who) + ": need L >= 1 and n = c 2^L");
     return BFC_EINVAL;
   }
   const int64_t c = n >> L;
-  const int ncol = r + p;
-  if (r < 1 || r > kLrRank || c < r || c > 64 || R < 1 || R > kLrR || p < 0 || ncol > kLrCols) {
-    set_error("bfc_lowrank_to_butterfly: need 1 <= r <= 8, r <= c <= 64, 1 <= R <= 16, "
+  if (r < 1 || r > kLrRank || c < r || c > 64 || R < 1 || R > kLrR || p < 0 ||
+      r + p > kLrCols) {
+    set_error(std::string(who) + ": need 1 <= r <= 8, r <= c <= 64, 1 <= R <= 16, "
               "0 <= p, r + p <= 32");
     return BFC_EINVAL;
   }
-  hipStream_t st = (hipStream_t)hip_stream;
+  return BFC_OK;
+}
+
+// Scratch values (complex128) the conversion needs: the projected factors of
+// two levels for each side and the sketches of one level.
+int64_t lr2bf_scratch_elems(int32_t L, int32_t r, int32_t R, int32_t p) {
+  const int64_t nb = (int64_t)1 << L;
+  return 4 * nb * r * R + nb * R * (r + p);
+}
+
+// Enqueues the whole conversion on st with buf as its scratch (every value of
+// it is written before it is read, so its contents on entry do not matter).
+// Allocates nothing.
+bfc_status lr2bf_enqueue(int64_t n, int32_t L, int32_t r, int32_t R, int32_t p, const double2* A,
+                         const double2* B, const double2* sk, double2* cores, double2* buf,
+                         hipStream_t st) {
+  const int64_t c = n >> L;
+  const int ncol = r + p;
   const int lr = (L + 1) / 2, lc = L / 2;
-  const double2* A = (const double2*)d_A;
-  const double2* B = (const double2*)d_B;
-  const double2* sk = (const double2*)d_sketches;
-  std::vector<const double2*> orow(lr + 1), ocol(lc + 1);
+  const double2* orow[13];  // L <= 24: at most 13 levels per side
+  const double2* ocol[13];
   int64_t off = 0;
   for (int l = 0; l <= lr; ++l) {
     orow[l] = sk + off;
@@ -329,46 +342,116 @@ extern "C" bfc_status bfc_lowrank_to_butterfly(int64_t n, int32_t L, int32_t r, 
   }
   const int64_t nb = (int64_t)1 << L;
   const int64_t fac = nb * r * R;  // projected factors of one level
-  const int64_t sks = nb * R * ncol;  // sketches of one level (at most 2^L blocks)
-  double2* buf = nullptr;
-  BFC_HIP_TRY(hipMalloc((void**)&buf, sizeof(double2) * (4 * fac + sks)));
   double2 *V0 = buf, *V1 = buf + fac, *W0 = buf + 2 * fac, *W1 = buf + 3 * fac, *S = buf + 4 * fac;
-  double2* cores = (double2*)d_cores_out;
   auto inner_core = [&](int m) { return cores + n * r + (int64_t)(m - 1) * (nb * 2) * r * r; };
   double2* last = cores + n * r + (int64_t)L * (nb * 2) * r * r;
-  bfc_status status = BFC_OK;
-  do {
-    // row leaves, sketched through B^T O
-    lr_sketch_kernel<<<(unsigned)(R * ncol), 256, 0, st>>>(B, R, orow[0], ncol, n, S);
-    lr_leaf_kernel<<<(unsigned)nb, 64, 0, st>>>(A, R, S, ncol, (int)c, r, cores, V0);
-    // column leaves, sketched through A^T O
-    lr_sketch_kernel<<<(unsigned)(R * ncol), 256, 0, st>>>(A, R, ocol[0], ncol, n, S);
-    lr_leaf_kernel<<<(unsigned)nb, 64, 0, st>>>(B, R, S, ncol, (int)c, r, last, W0);
-    if (hipGetLastError() != hipSuccess) {
-      status = BFC_EHIP;
-      break;
+  // row leaves, sketched through B^T O
+  lr_sketch_kernel<<<(unsigned)(R * ncol), 256, 0, st>>>(B, R, orow[0], ncol, n, S);
+  lr_leaf_kernel<<<(unsigned)nb, 64, 0, st>>>(A, R, S, ncol, (int)c, r, cores, V0);
+  // column leaves, sketched through A^T O
+  lr_sketch_kernel<<<(unsigned)(R * ncol), 256, 0, st>>>(A, R, ocol[0], ncol, n, S);
+  lr_leaf_kernel<<<(unsigned)nb, 64, 0, st>>>(B, R, S, ncol, (int)c, r, last, W0);
+  if (hipGetLastError() != hipSuccess) return BFC_EHIP;
+  for (int l = 1; l <= lr; ++l) {
+    lr_sketch_kernel<<<(unsigned)(((int64_t)1 << l) * R * ncol), 256, 0, st>>>(
+        B, R, orow[l], ncol, n >> l, S);
+    lr_inner_kernel<<<(unsigned)nb, 64, 0, st>>>(V0, R, S, ncol, r, L, l, 0, inner_core(l), V1);
+    std::swap(V0, V1);
+  }
+  for (int l = 1; l <= lc; ++l) {
+    lr_sketch_kernel<<<(unsigned)(((int64_t)1 << l) * R * ncol), 256, 0, st>>>(
+        A, R, ocol[l], ncol, n >> l, S);
+    lr_inner_kernel<<<(unsigned)nb, 64, 0, st>>>(W0, R, S, ncol, r, L, l, 1,
+                                                 inner_core(L + 1 - l), W1);
+    std::swap(W0, W1);
+  }
+  const int64_t rows = nb * 2 * r;
+  lr_middle_kernel<<<blocks_for(rows, 256), 256, 0, st>>>(inner_core(lr), V0, W0, r, R, lr, rows);
+  if (hipGetLastError() != hipSuccess) return BFC_EHIP;
+  return BFC_OK;
+}
+
+// Scratch of bfc_lowrank_to_butterfly_noalloc: kLrScratchBytes of device
+// memory per GPU the library runs on, held until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): its device address is looked up once per
+// device with hipGetSymbolAddress, on that device's first call, and kept.
+constexpr int64_t kLrScratchBytes = int64_t(16) << 20;
+static __device__ __align__(256) double scratch[kLrScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+bfc_status scratch_of_current_device(double2** out) {
+  int dev = -1;
+  BFC_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("bfc_lowrank_to_butterfly_noalloc: device index out of range");
+    return BFC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("bfc_lowrank_to_butterfly_noalloc: hipGetSymbolAddress: ") +
+                hipGetErrorString(e));
+      return BFC_EHIP;
     }
-    for (int l = 1; l <= lr; ++l) {
-      lr_sketch_kernel<<<(unsigned)(((int64_t)1 << l) * R * ncol), 256, 0, st>>>(
-          B, R, orow[l], ncol, n >> l, S);
-      lr_inner_kernel<<<(unsigned)nb, 64, 0, st>>>(V0, R, S, ncol, r, L, l, 0, inner_core(l), V1);
-      std::swap(V0, V1);
-    }
-    for (int l = 1; l <= lc; ++l) {
-      lr_sketch_kernel<<<(unsigned)(((int64_t)1 << l) * R * ncol), 256, 0, st>>>(
-          A, R, ocol[l], ncol, n >> l, S);
-      lr_inner_kernel<<<(unsigned)nb, 64, 0, st>>>(W0, R, S, ncol, r, L, l, 1,
-                                                   inner_core(L + 1 - l), W1);
-      std::swap(W0, W1);
-    }
-    const int64_t rows = nb * 2 * r;
-    lr_middle_kernel<<<blocks_for(rows, 256), 256, 0, st>>>(inner_core(lr), V0, W0, r, R, lr, rows);
-    if (hipGetLastError() != hipSuccess) status = BFC_EHIP;
-  } while (false);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (double2*)g_scratch_ptr[dev];
+  return BFC_OK;
+}
+
+}  // namespace
+}  // namespace bfc
+
+using namespace bfc;
+
+extern "C" bfc_status bfc_lowrank_to_butterfly(int64_t n, int32_t L, int32_t r, int32_t R,
+                                               int32_t p, const void* d_A, const void* d_B,
+                                               const void* d_sketches, void* d_cores_out,
+                                               void* hip_stream) {
+  set_error("");
+  BFC_TRY(lr2bf_check(n, L, r, R, p, d_A, d_B, d_sketches, d_cores_out,
+                      "bfc_lowrank_to_butterfly"));
+  hipStream_t st = (hipStream_t)hip_stream;
+  double2* buf = nullptr;
+  BFC_HIP_TRY(hipMalloc((void**)&buf, sizeof(double2) * lr2bf_scratch_elems(L, r, R, p)));
+  const bfc_status status =
+      lr2bf_enqueue(n, L, r, R, p, (const double2*)d_A, (const double2*)d_B,
+                    (const double2*)d_sketches, (double2*)d_cores_out, buf, st);
   const hipError_t e = hipStreamSynchronize(st);
-  hipFree(buf);
+  (void)hipFree(buf);
   if (status != BFC_OK || e != hipSuccess) {
     set_error("bfc_lowrank_to_butterfly: a kernel launch failed");
+    return BFC_EHIP;
+  }
+  return BFC_OK;
+}
+
+extern "C" bfc_status bfc_lowrank_to_butterfly_noalloc(int64_t n, int32_t L, int32_t r, int32_t R,
+                                                       int32_t p, const void* d_A, const void* d_B,
+                                                       const void* d_sketches, void* d_cores_out,
+                                                       void* hip_stream) {
+  set_error("");
+  BFC_TRY(lr2bf_check(n, L, r, R, p, d_A, d_B, d_sketches, d_cores_out,
+                      "bfc_lowrank_to_butterfly_noalloc"));
+  const int64_t need = lr2bf_scratch_elems(L, r, R, p) * (int64_t)sizeof(double2);
+  if (need > kLrScratchBytes) {
+    set_error("bfc_lowrank_to_butterfly_noalloc: needs " + std::to_string(need) +
+              " bytes of scratch, above the " + std::to_string(kLrScratchBytes) +
+              "-byte maximum (2^L (4 r R + R (r + p)) complex128 values); use "
+              "bfc_lowrank_to_butterfly");
+    return BFC_EINVAL;
+  }
+  double2* buf = nullptr;
+  BFC_TRY(scratch_of_current_device(&buf));
+  if (lr2bf_enqueue(n, L, r, R, p, (const double2*)d_A, (const double2*)d_B,
+                    (const double2*)d_sketches, (double2*)d_cores_out, buf,
+                    (hipStream_t)hip_stream) != BFC_OK) {
+    set_error("bfc_lowrank_to_butterfly_noalloc: a kernel launch failed");
     return BFC_EHIP;
   }
   return BFC_OK;

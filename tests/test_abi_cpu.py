@@ -109,3 +109,14 @@ def test_item_size_argument_checks():
     assert lib.bfc_autotune_item_size(None, 1, 1, None, 0, ctypes.byref(chosen), None,
                                       None) == _lib.BFC_EINVAL
 
+
+def test_noalloc_conversion_argument_checks():
+    # rejected on the host before any HIP call: null pointers, bad shapes and
+    # sizes beyond the 16 MiB scratch (fake pointers are never dereferenced)
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x1000)
+    f = lib.bfc_lowrank_to_butterfly_noalloc
+    assert f(1024, 4, 6, 6, 4, None, fake, fake, fake, None) == _lib.BFC_EINVAL
+    assert f(1024, 4, 9, 6, 4, fake, fake, fake, fake, None) == _lib.BFC_EINVAL
+    assert f(262144, 12, 8, 8, 4, fake, fake, fake, fake, None) == _lib.BFC_EINVAL
+    assert "maximum" in lib.bfc_last_error().decode()
