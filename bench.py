@@ -947,15 +947,18 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         lp.close()
-        res = ws.evaluate(net, list(range(900000, 900000 + n_eval)), device=dev, log=log)
+        res = ws.evaluate(net, list(range(900000, 900000 + n_eval)), device=dev, log=log,
+                          starts=("learned", "lowrank", "random", "learned+fallback"))
         summ = ws.summarize(res)
         batched = ws.evaluate_batched(net, list(range(900000, 900000 + n_eval)), device=dev,
                                       log=log)
         prec = ws.precision_check(net, list(range(900000, 900000 + min(n_eval, 20))), device=dev)
-        gain = None
+        gain = gain_random = None
         if summ["learned"]["mean_sweeps_capped"]:
             gain = round(summ["lowrank"]["mean_sweeps_capped"] /
                          summ["learned"]["mean_sweeps_capped"], 3)
+            gain_random = round(summ["random"]["mean_sweeps_capped"] /
+                                summ["learned"]["mean_sweeps_capped"], 3)
         return {"n": ws.WARM_N, "L": ws.WARM_L, "r": ws.WARM_R, "nnz": ws.nnz_for(ws.WARM_N),
                 "train_instances": n_train, "epochs": epochs, "held_out": n_eval,
                 "network": "4 dense layers, width 512, ReLU; FP32 training, BF16 inference",
@@ -964,7 +967,12 @@ def main():
                 "target_test_err": 1e-3, "max_sweeps": 150, "starts": summ,
                 "batched_chunks_of_50": batched,
                 "complex64_vs_complex128": prec,
-                "sweeps_ratio_lowrank_over_learned": gain}
+                "sweeps_ratio_lowrank_over_learned": gain,
+                "sweeps_ratio_random_over_learned": gain_random,
+                "fallback": "learned+fallback: the Sec. 5.2 guess is swept too when the "
+                            "learned start's training error after 20 sweeps is not below "
+                            "1e-3 (or a solve failed); the run continues from the start "
+                            "with the lower training error"}
 
     if not args.no_learned:
         out["learned_warm_start"] = learned_record(args.learned_train, args.learned_epochs,

@@ -191,6 +191,20 @@ bfc_status bfc_residual(const bfc_problem* p, int64_t m, const int32_t* d_rows,
  */
 bfc_status bfc_residual_observed(bfc_problem* p, double out_sq[2], void* hip_stream);
 
+/*
+ * The relative error of eq. (BF_convergence), ||P(T - X)|| / ||P T||, over
+ * the listed entries (bfc_relative_error, arguments as bfc_residual) or over
+ * the problem's own observed entries (bfc_relative_error_observed, the
+ * training error, as bfc_residual_observed): sqrt(out_sq[0] / out_sq[1])
+ * from the two FP64 norms (sqrt(out_sq[0]) when ||P T|| = 0), written to
+ * *out (HOST).  Synchronizes; returns ENOTSPD, after writing *out, when solve
+ * failures were pending (and clears them), like the residual calls.
+ */
+bfc_status bfc_relative_error(const bfc_problem* p, int64_t m, const int32_t* d_rows,
+                              const int32_t* d_cols, const void* d_vals, double* out,
+                              void* hip_stream);
+bfc_status bfc_relative_error_observed(bfc_problem* p, double* out, void* hip_stream);
+
 /* Copy the cores out to / in from d_cores (bfc_num_params complex128 values). */
 bfc_status bfc_get_cores(const bfc_problem* p, void* d_cores, void* hip_stream);
 bfc_status bfc_set_cores(bfc_problem* p, const void* d_cores, void* hip_stream);

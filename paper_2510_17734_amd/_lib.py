@@ -47,6 +47,8 @@ EXPORTS = (
     "bfc_core_stats",
     "bfc_solve_counters",
     "bfc_residual_observed",
+    "bfc_relative_error",
+    "bfc_relative_error_observed",
     "bfc_use_graphs",
     "bfc_batch_create",
     "bfc_batch_sweep",
@@ -113,6 +115,10 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_predict_entries.argtypes = [P, i64, vp, vp, vp, vp]
     lib.bfc_predict_entries.restype = i32
     lib.bfc_residual.argtypes = [P, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_relative_error.argtypes = [P, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_relative_error.restype = i32
+    lib.bfc_relative_error_observed.argtypes = [P, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_relative_error_observed.restype = i32
     lib.bfc_residual.restype = i32
     lib.bfc_get_cores.argtypes = [P, vp, vp]
     lib.bfc_get_cores.restype = i32

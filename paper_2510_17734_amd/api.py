@@ -187,9 +187,40 @@ def residual_observed(p: Problem, stream=None):
     return float(out[0]), float(out[1])
 
 
+def relative_error_status(p: Problem, rows=None, cols=None, vals=None, stream=None):
+    """(relative error, status): bfc_relative_error over the listed entries,
+    or bfc_relative_error_observed (the training error) when rows is None.
+    The status is BFC_OK or BFC_ENOTSPD (pending solve failures, reported
+    and cleared); other errors raise."""
+    out = ctypes.c_double()
+    lib = _lib.load()
+    if rows is None:
+        code = lib.bfc_relative_error_observed(p.handle, ctypes.byref(out), _stream(stream))
+        where = "bfc_relative_error_observed"
+    else:
+        r_t = _dev_i32(rows, p.device)
+        c_t = _dev_i32(cols, p.device)
+        v_t = _dev_c128(vals, p.device)
+        code = lib.bfc_relative_error(p.handle, int(r_t.numel()), _ptr(r_t), _ptr(c_t), _ptr(v_t),
+                                      ctypes.byref(out), _stream(stream))
+        where = "bfc_relative_error"
+    if code not in (0, _lib.BFC_ENOTSPD):
+        raise BfcError(code, where)
+    return float(out.value), int(code)
+
+
 def relative_error(p: Problem, rows, cols, vals, stream=None) -> float:
-    num, den = residual(p, rows, cols, vals, stream)
-    return (num / den) ** 0.5 if den > 0 else num ** 0.5
+    """bfc_relative_error (eq. (BF_convergence)); raises on pending solve failures."""
+    err, code = relative_error_status(p, rows, cols, vals, stream)
+    _check(code, "bfc_relative_error")
+    return err
+
+
+def train_error(p: Problem, stream=None) -> float:
+    """bfc_relative_error_observed: the training error; raises on pending solve failures."""
+    err, code = relative_error_status(p, stream=stream)
+    _check(code, "bfc_relative_error_observed")
+    return err
 
 
 def get_cores(p: Problem, out=None, stream=None) -> torch.Tensor:

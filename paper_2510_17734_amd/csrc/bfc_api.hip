@@ -1,4 +1,5 @@
 // extern "C" entry points of libbfc (declared in include/bfc.h).
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -390,6 +391,34 @@ bfc_status bfc_residual(const bfc_problem* p, int64_t m, const int32_t* d_rows,
     return BFC_ENOTSPD;
   }
   return BFC_OK;
+}
+
+// eq. (BF_convergence): sqrt(num / den) from the two norms, sqrt(num) when
+// den = 0; the status of the residual call is passed on (ENOTSPD after
+// filling *out).
+static bfc_status relative_from(bfc_status s, const double sq[2], double* out) {
+  if (s == BFC_OK || s == BFC_ENOTSPD) *out = sq[1] > 0.0 ? sqrt(sq[0] / sq[1]) : sqrt(sq[0]);
+  return s;
+}
+
+bfc_status bfc_relative_error(const bfc_problem* p, int64_t m, const int32_t* d_rows,
+                              const int32_t* d_cols, const void* d_vals, double* out,
+                              void* hip_stream) {
+  if (!out) {
+    set_error("bad relative-error arguments");
+    return BFC_EINVAL;
+  }
+  double sq[2] = {0.0, 0.0};
+  return relative_from(bfc_residual(p, m, d_rows, d_cols, d_vals, sq, hip_stream), sq, out);
+}
+
+bfc_status bfc_relative_error_observed(bfc_problem* p, double* out, void* hip_stream) {
+  if (!out) {
+    set_error("bad relative-error arguments");
+    return BFC_EINVAL;
+  }
+  double sq[2] = {0.0, 0.0};
+  return relative_from(bfc_residual_observed(p, sq, hip_stream), sq, out);
 }
 
 bfc_status bfc_residual_observed(bfc_problem* p, double out_sq[2], void* hip_stream) {

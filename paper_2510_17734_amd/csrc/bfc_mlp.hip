@@ -1,10 +1,10 @@
 // Dense layers of the warm-start network: forward, backward and ADAM for
 // FP32 training, a BF16-input forward for inference.  Every product is one
-// LDS-tiled MFMA kernel: a 64 x 64 output tile per 256-thread workgroup,
-// k-slabs of 16 staged through LDS (loaded along whichever operand dimension
-// is contiguous; BF16 operands widened to FP32 on the way, which is exact),
-// each wavefront a 32 x 32 quarter as 2 x 2 FP32 MFMA 16x16x4 blocks, bias and
-// activation fused into the store.  The ReLU derivative of the backward pass
+// LDS-tiled MFMA kernel with a 64 x 64 output tile per 256-thread workgroup,
+// each wavefront a 32 x 32 quarter as 2 x 2 MFMA blocks, bias and activation
+// fused into the store: FP32 MFMA 16x16x4 on k-slabs of 16 for training
+// (loaded along whichever operand dimension is contiguous), BF16 MFMA
+// 16x16x32 with FP32 accumulation on k-slabs of 32 for inference.  The ReLU derivative of the backward pass
 // is applied while the gradient operand is loaded, so dZ = dY * (Y > 0) is
 // never stored.
 #include <hip/hip_runtime.h>
@@ -22,9 +22,6 @@ namespace {
 constexpr int kTile = 64, kSlab = 16, kPad = 4;
 
 __device__ inline float load_as_float(const float* p, int64_t i) { return p[i]; }
-__device__ inline float load_as_float(const uint16_t* p, int64_t i) {
-  return __uint_as_float((uint32_t)p[i] << 16);
-}
 
 // round to nearest even (finite inputs)
 __device__ inline uint16_t to_bf16(float f) {
@@ -104,6 +101,83 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<float>::step(xa[x], yb[y], acc[x][y]);
     }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = i0 + wr * 32 + x * 16 + Mfma<float>::out_row(lane, v);
+        const int64_t gj = j0 + wc * 32 + y * 16 + (lane & 15);
+        if (gi >= M || gj >= N) continue;
+        float o = acc[x][y][v] + (bias ? bias[gj] : 0.f);
+        if (act == 1) o = o > 0.f ? o : 0.f;
+        if (C) C[gi * ldc + gj] = o;
+        if (Ch) Ch[gi * ldc + gj] = to_bf16(o);
+      }
+}
+
+// Inference product on the BF16 matrix cores: C = act(Xh Wh + bias) with Xh
+// (M x K, row-major) and Wh (K x N, row-major) in BF16, FP32 accumulation.
+// A 64 x 64 output tile per 256-thread workgroup, k-slabs of 32 (the depth
+// of the 16x16x32 BF16 instruction) staged in LDS with k contiguous for both
+// operands (Wh is transposed on the way in), so each lane reads its eight
+// consecutive k values of a row or column as one 16-byte vector: lane l
+// supplies A[l%16][8(l/16)..8(l/16)+7] and B[8(l/16)..8(l/16)+7][l%16].  Each
+// wavefront computes a 32 x 32 quarter as 2 x 2 blocks; the output layout is
+// the FP32 16x16x4 instruction's.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+constexpr int kSlabH = 32, kLdH = kSlabH + 8;  // padded row of a staged slab (80 bytes)
+
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int64_t M, int64_t N, int64_t K,
+                                                        const uint16_t* X, const uint16_t* W,
+                                                        const float* bias, int act, float* C,
+                                                        uint16_t* Ch, int64_t ldc) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kTile * kLdH];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile * kLdH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int64_t i0 = (int64_t)blockIdx.y * kTile, j0 = (int64_t)blockIdx.x * kTile;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = 0; k0 < K; k0 += kSlabH) {
+    {  // A: thread -> row tid / 4, eight k values from (tid % 4) * 8
+      const int o = tid >> 2, kk = (tid & 3) * 8;
+      const int64_t gi = i0 + o;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t gk = k0 + kk + t;
+        As[o * kLdH + kk + t] = (gi < M && gk < K) ? X[gi * K + gk] : (uint16_t)0;
+      }
+    }
+    {  // B: thread -> k row tid / 8, eight consecutive columns from (tid % 8) * 8
+      const int kk = tid >> 3, o = (tid & 7) * 8;
+      const int64_t gk = k0 + kk;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t gj = j0 + o + t;
+        Bs[(o + t) * kLdH + kk] = (gj < N && gk < K) ? W[gk * N + gj] : (uint16_t)0;
+      }
+    }
+    __syncthreads();
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
+    bf16x8_t xa[2], yb[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      xa[x] = *(const bf16x8_t*)(As + (wr * 32 + x * 16 + r16) * kLdH + kq);
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      yb[y] = *(const bf16x8_t*)(Bs + (wc * 32 + y * 16 + r16) * kLdH + kq);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[x], yb[y], acc[x][y], 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
@@ -223,8 +297,16 @@ bfc_status bfc_mlp_forward_bf16(int64_t m, int64_t k, int64_t n, const uint16_t*
     set_error("bad bfc_mlp_forward_bf16 arguments");
     return BFC_EINVAL;
   }
-  return gemm<uint16_t>(m, n, k, Operand{Xh, k, 1, nullptr}, Operand{Wh, 1, n, nullptr}, b, act,
-                        Y, Yh, n, (hipStream_t)hip_stream);
+  if (m == 0 || n == 0) return BFC_OK;
+  const int64_t gx = (n + kTile - 1) / kTile, gy = (m + kTile - 1) / kTile;
+  if (gx > 0x7FFFFFFF || gy > 65535) {
+    set_error("bfc_mlp: matrix too large for one launch");
+    return BFC_EINVAL;
+  }
+  gemm_bf16_kernel<<<dim3((unsigned)gx, (unsigned)gy), 256, 0, (hipStream_t)hip_stream>>>(
+      m, n, k, Xh, Wh, b, act, Y, Yh, n);
+  BFC_HIP_TRY(hipGetLastError());
+  return BFC_OK;
 }
 
 bfc_status bfc_mlp_to_bf16(int64_t count, const float* src, uint16_t* dst, void* hip_stream) {

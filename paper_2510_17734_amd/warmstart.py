@@ -129,6 +129,7 @@ def _complete(prob, vals, n, L, r, seed, sweeps):
     bfc.set_cores(prob, random_cores(n, L, r, seed, scale=rms * math.sqrt(r)))
     for _ in range(sweeps):
         bfc.sweep(prob)
+    bfc.sync_status(prob)  # a training completion with failed solves is an error
 
 
 def make_dataset(count: int, first_seed: int, *, sweeps: int = 40, pattern_seed: int = 77,
@@ -208,6 +209,64 @@ def _lowrank_guess(inst, prob_lr_cfg, device, sweeps=3, p=4):
     return flat, time.perf_counter() - t0
 
 
+def run_from_proposal(prob, proposal, guess, *, test, target: float = 1e-3,
+                      max_sweeps: int = 150, judge_sweeps: int = 20, judge_err: float = 1e-3):
+    """ALS from the network's proposal with the Sec. 5.2 guess as the fallback,
+    judged by the ALS training residuals (never by the test entries).
+
+    proposal: FP32 cores (bfc_set_cores_f32 layout); guess: a callable
+    returning the guess's complex128 cores (computed only when needed).
+    Sweeps run from the proposal until the test error reaches `target` (the
+    evaluation's measure) or `judge_sweeps` sweeps are done.  If by then the
+    training error (eq. (BF_convergence) on the observed entries) is not
+    below `judge_err` -- or a solve failed, or it is not finite -- the guess
+    is swept `judge_sweeps` times as well and the run continues from
+    whichever start has the lower training error.  Every sweep counts
+    against `max_sweeps`.  Returns sweeps to the target (None if missed),
+    the final test error, whether the guess was tried and which start won."""
+    bfc.set_cores_f32(prob, proposal)
+    used, winner = 0, "learned"
+    failed = False  # a solve failed during the current phase
+    err, st = bfc.relative_error_status(prob, *test)
+
+    def sweeps_until(limit):
+        nonlocal used, err, failed
+        while used < limit:
+            bfc.sweep(prob)
+            used += 1
+            err, code = bfc.relative_error_status(prob, *test)
+            failed = failed or code != 0
+            if err <= target:
+                return True
+        return False
+
+    def judged():  # the phase's training error; inf if a solve failed or it is not finite
+        tr, code = bfc.relative_error_status(prob)
+        return tr if (not failed and code == 0 and math.isfinite(tr)) else math.inf
+
+    if sweeps_until(min(judge_sweeps, max_sweeps)):
+        return {"sweeps": used, "final_err": err, "fallback_tried": False, "start": winner}
+    tr_learned = judged()
+    if tr_learned < judge_err:
+        hit = sweeps_until(max_sweeps)
+        return {"sweeps": used if hit else None, "final_err": err, "fallback_tried": False,
+                "start": winner}
+    kept = bfc.get_cores(prob).clone()
+    bfc.set_cores(prob, guess())
+    failed = False
+    if sweeps_until(min(used + judge_sweeps, max_sweeps)):
+        return {"sweeps": used, "final_err": err, "fallback_tried": True, "start": "lowrank"}
+    tr_guess = judged()
+    if tr_guess <= tr_learned:
+        winner = "lowrank"
+    else:
+        bfc.set_cores(prob, kept)
+        err, _ = bfc.relative_error_status(prob, *test)
+    hit = err <= target or sweeps_until(max_sweeps)
+    return {"sweeps": used if hit else None, "final_err": err, "fallback_tried": True,
+            "start": winner}
+
+
 def evaluate(net: WarmStartNet | None, seeds, *, target: float = 1e-3, max_sweeps: int = 150,
              device="cuda:0", log=None, starts=("learned", "lowrank", "random")):
     """Sweeps and time to `target` test error from each start, on instances
@@ -216,6 +275,7 @@ def evaluate(net: WarmStartNet | None, seeds, *, target: float = 1e-3, max_sweep
     cfg = bfc.Config(n=n, L=L, r=r, precision="c64")
     lr_cfg = bfc.Config(n=n, L=0, r=r, precision="c64", reg_rel=1e-6)
     res = {s: [] for s in starts}
+    fb = {"tried": 0, "lowrank_won": 0}
     for i, seed in enumerate(seeds):
         w, d, s_ = warm_params(seed)
         rows, cols, trows, tcols = sample_pairs(n, nnz_for(n), 1000, seed + 500009)
@@ -233,6 +293,22 @@ def evaluate(net: WarmStartNet | None, seeds, *, target: float = 1e-3, max_sweep
         for start in starts:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            if start == "learned+fallback":
+                x = features(w, d, s_, observed_histogram(n, rows_d, cols_d,
+                                                          torch.as_tensor(vals, device=device)))
+                out = net.infer_bf16(x.reshape(1, -1).contiguous()).reshape(-1)
+                run = run_from_proposal(prob, out, lambda: _lowrank_guess(inst, lr_cfg, device)[0],
+                                        test=tr, target=target, max_sweeps=max_sweeps)
+                torch.cuda.synchronize()
+                spent = time.perf_counter() - t0
+                fb["tried"] += run["fallback_tried"]
+                fb["lowrank_won"] += run["start"] == "lowrank"
+                res[start].append({"seed": seed, "start_err": float("nan"), "sweeps": run["sweeps"],
+                                   "time_s": spent if run["sweeps"] else None,
+                                   "final_err": run["final_err"], "start_s": 0.0,
+                                   "fallback_tried": run["fallback_tried"],
+                                   "winner": run["start"]})
+                continue
             if start == "learned":
                 x = features(w, d, s_, observed_histogram(n, rows_d, cols_d,
                                                           torch.as_tensor(vals, device=device)))
@@ -264,6 +340,8 @@ def evaluate(net: WarmStartNet | None, seeds, *, target: float = 1e-3, max_sweep
         prob.close()
         if log and (i + 1) % 25 == 0:
             log(f"evaluated {i + 1}/{len(seeds)}")
+    if "learned+fallback" in res:
+        res["fallback_counts"] = fb
     return res
 
 
@@ -273,6 +351,9 @@ def summarize(res, max_sweeps: int = 150):
     it, median starting test error."""
     out = {}
     for start, rows in res.items():
+        if start == "fallback_counts":
+            out[start] = rows
+            continue
         hits = [x for x in rows if x["sweeps"] is not None]
         out[start] = {
             "reached": len(hits), "instances": len(rows),
@@ -281,8 +362,8 @@ def summarize(res, max_sweeps: int = 150):
             "mean_sweeps_capped": float(np.mean([x["sweeps"] or max_sweeps for x in rows]))
             if rows else None,
             "mean_time_to_target_s": float(np.mean([x["time_s"] for x in hits])) if hits else None,
-            "median_start_test_err": float(np.median([x["start_err"] for x in rows]))
-            if rows else None,
+            "median_start_test_err": float(np.nanmedian([x["start_err"] for x in rows]))
+            if rows and not all(math.isnan(x["start_err"]) for x in rows) else None,
             "mean_start_s": float(np.mean([x["start_s"] for x in rows])) if rows else None,
         }
     return out
@@ -324,6 +405,22 @@ def evaluate_batched(net: WarmStartNet, seeds, *, chunk: int = 50, target: float
         for start in starts:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            if start == "learned+fallback":
+                x = features(w, d, s_, observed_histogram(n, rows_d, cols_d,
+                                                          torch.as_tensor(vals, device=device)))
+                out = net.infer_bf16(x.reshape(1, -1).contiguous()).reshape(-1)
+                run = run_from_proposal(prob, out, lambda: _lowrank_guess(inst, lr_cfg, device)[0],
+                                        test=tr, target=target, max_sweeps=max_sweeps)
+                torch.cuda.synchronize()
+                spent = time.perf_counter() - t0
+                fb["tried"] += run["fallback_tried"]
+                fb["lowrank_won"] += run["start"] == "lowrank"
+                res[start].append({"seed": seed, "start_err": float("nan"), "sweeps": run["sweeps"],
+                                   "time_s": spent if run["sweeps"] else None,
+                                   "final_err": run["final_err"], "start_s": 0.0,
+                                   "fallback_tried": run["fallback_tried"],
+                                   "winner": run["start"]})
+                continue
             if start == "learned":
                 X = torch.stack([features(x["w"], x["d"], x["s"], x["hist"]) for x in insts])
                 prop = net.infer_bf16(X.contiguous())

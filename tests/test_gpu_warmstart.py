@@ -173,11 +173,12 @@ def test_set_values_and_f32_cores():
     prob.close()
 
 
-def test_trained_network_beats_the_lowrank_guess():
+def test_trained_network_beats_the_lowrank_guess_and_random_starts():
     """A short training run (128 completions, 10 epochs) already lowers the
     training loss and, on 12 held-out operators, needs fewer sweeps to test
-    error 1e-3 on average than the Sec. 5.2 initial guess (a miss counts as
-    the 150-sweep cap)."""
+    error 1e-3 on average than the Sec. 5.2 initial guess and than random
+    starts (a miss counts as the 150-sweep cap); with the guess as the
+    fallback it misses no more instances than either."""
     from paper_2510_17734_amd import warmstart as ws
     ds, lp, central = ws.make_dataset(128, 1000, device=DEV)
     net = ws.WarmStartNet(ws.N_FEATURES, central.numel(), out_bias=central, device=DEV)
@@ -185,8 +186,78 @@ def test_trained_network_beats_the_lowrank_guess():
     lp.close()
     assert hist[-1] < 0.9 * hist[0], hist
     summ = ws.summarize(ws.evaluate(net, list(range(900000, 900012)), device=DEV,
-                                    starts=("learned", "lowrank")))
-    assert summ["learned"]["mean_sweeps_capped"] < summ["lowrank"]["mean_sweeps_capped"], summ
+                                    starts=("learned", "lowrank", "random", "learned+fallback")))
+    learned = summ["learned"]["mean_sweeps_capped"]
+    assert learned < summ["lowrank"]["mean_sweeps_capped"], summ
+    assert learned < summ["random"]["mean_sweeps_capped"], summ
+    assert summ["learned+fallback"]["reached"] >= min(summ["learned"]["reached"],
+                                                      summ["lowrank"]["reached"]), summ
+
+
+def _warm_instance(seed):
+    from paper_2510_17734_amd import warmstart as ws
+    from workloads import gaussian_sketches, green_geom_entries, warm_params
+    n, L, r = ws.WARM_N, ws.WARM_L, ws.WARM_R
+    w, d, s_ = warm_params(seed)
+    rows, cols, trows, tcols = sample_pairs(n, ws.nnz_for(n), 1000, seed + 500009)
+    vals = green_geom_entries(n, w, d, s_, rows, cols)
+    test = tuple(torch.as_tensor(a, device=DEV)
+                 for a in (trows, tcols, green_geom_entries(n, w, d, s_, trows, tcols)))
+    inst = {"rows": rows, "cols": cols, "vals": vals, "seed": seed,
+            "sketches": gaussian_sketches(n, L, r, 4, seed=seed + 3)}
+    prob = bfc.init_cores(bfc.Config(n=n, L=L, r=r, precision="c64"), rows, cols, vals,
+                          random_cores(n, L, r, seed + 7), device=DEV)
+    lr_cfg = bfc.Config(n=n, L=0, r=r, precision="c64", reg_rel=1e-6)
+    guess = lambda: ws._lowrank_guess(inst, lr_cfg, DEV)[0]
+    return prob, test, guess
+
+
+@pytest.mark.parametrize("bad", ["zero", "nan"])
+def test_fallback_to_the_lowrank_guess_when_the_proposal_fails(bad):
+    """A proposal whose sweeps go nowhere (all-zero cores: every system is
+    singular; NaN cores: a diverged network) is judged by its training
+    residuals after 20 sweeps and replaced by the Sec. 5.2 guess, and the run
+    then follows exactly the guess's own sweeps."""
+    from paper_2510_17734_amd import warmstart as ws
+    prob, test, guess = _warm_instance(900101)
+    m = 2 * bfc.num_params(ws.WARM_N, ws.WARM_L, ws.WARM_R)
+    proposal = torch.zeros(m, dtype=torch.float32, device=DEV)
+    if bad == "nan":
+        proposal[::7] = float("nan")
+    run = ws.run_from_proposal(prob, proposal, guess, test=test, max_sweeps=80)
+    assert run["fallback_tried"] and run["start"] == "lowrank", run
+    # the guess alone, from the same cores, with the 20 sweeps the proposal used
+    bfc.set_cores(prob, guess())
+    bfc.sync_status(prob)
+    direct, err = None, None
+    for k in range(60):
+        bfc.sweep(prob)
+        err = bfc.relative_error(prob, *test)
+        if err <= 1e-3:
+            direct = k + 1
+            break
+    assert (run["sweeps"] is None) == (direct is None)
+    if direct is not None:
+        assert run["sweeps"] == 20 + direct
+    assert run["final_err"] == err
+    prob.close()
+
+
+def test_no_fallback_from_a_good_proposal():
+    """The instance's own completion as the proposal reaches the target at
+    once; the guess is never computed."""
+    from paper_2510_17734_amd import warmstart as ws
+    prob, test, guess = _warm_instance(900102)
+    for _ in range(150):
+        bfc.sweep(prob)
+    own = bfc.relative_error(prob, *test)
+    good = torch.view_as_real(bfc.get_cores(prob)).reshape(-1).to(torch.float32).contiguous()
+    calls = []
+    run = ws.run_from_proposal(prob, good, lambda: calls.append(1) or guess(), test=test)
+    assert not run["fallback_tried"] and run["start"] == "learned" and not calls, run
+    if own <= 0.5e-3:  # a converged completion stays converged through the FP32 round trip
+        assert run["sweeps"] is not None and run["sweeps"] <= 3, (run, own)
+    prob.close()
 
 
 def test_layers_without_bias_and_bf16_only_output():
