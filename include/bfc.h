@@ -286,6 +286,33 @@ bfc_status bfc_profile_read(bfc_problem* p, int32_t kind, double* total_ms, int6
  */
 bfc_status bfc_core_stats(const bfc_problem* p, int32_t core, int64_t out[7]);
 
+/*
+ * Debug checks: every invariant the kernels rely on when they index the
+ * problem's layout, recomputed on the host from the stored entries -- each
+ * core's sorted copy a permutation of core 0's (same index pairs and
+ * values), every entry in the block its key names (row, slice key
+ * ((ib >> (m-1)) << m) | (jb >> (L-m)), column), block offsets spanning the
+ * entries, inner slices sorted by their grouping index, subgroups of 1 to 8
+ * entries sharing a row (or column) inside one slice, work items tiling each
+ * slice's subgroups, and the environment trie (node tables strictly
+ * increasing, every entry pointing at the node of its own (ib >> p, j) or
+ * (jb >> (L-p+1), i), every node at its parent on the adjacent level).
+ * Synchronizes the device and copies the arrays to the host (O(nnz L) host
+ * work); launches no kernel.  BFC_OK, or BFC_EINVAL with bfc_last_error()
+ * naming the first violation (core and position).
+ */
+bfc_status bfc_validate(const bfc_problem* p);
+
+/*
+ * Test hook for the out-of-memory paths: after `count` more device
+ * allocations by the library succeed, the next one fails as if the device
+ * were out of memory (the call making it returns BFC_ENOMEM and releases what
+ * it had allocated), and allocations then behave normally again.  count < 0
+ * turns the hook off (the default).  Returns the previous setting.  Process
+ * wide; not for concurrent use.
+ */
+int64_t bfc_debug_fail_allocation_after(int64_t count);
+
 /* Release every device allocation of the problem.  NULL is ignored. */
 void bfc_destroy(bfc_problem* p);
 

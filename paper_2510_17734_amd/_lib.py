@@ -57,6 +57,8 @@ EXPORTS = (
     "bfc_set_item_size",
     "bfc_autotune_item_size",
     "bfc_lowrank_to_butterfly",
+    "bfc_validate",
+    "bfc_debug_fail_allocation_after",
     "bfc_lowrank_to_butterfly_noalloc",
     "bfc_adam_sweep",
     "bfc_adam_reset",
@@ -157,6 +159,10 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.bfc_autotune_item_size.restype = i32
     lib.bfc_lowrank_to_butterfly.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.bfc_lowrank_to_butterfly.restype = i32
+    lib.bfc_validate.argtypes = [P]
+    lib.bfc_validate.restype = i32
+    lib.bfc_debug_fail_allocation_after.argtypes = [i64]
+    lib.bfc_debug_fail_allocation_after.restype = i64
     lib.bfc_lowrank_to_butterfly_noalloc.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.bfc_lowrank_to_butterfly_noalloc.restype = i32
     d = ctypes.c_double

@@ -289,6 +289,17 @@ def solve_counters(p: Problem, reset: bool = False, stream=None):
     return int(out[0]), int(out[1])
 
 
+def validate(p: Problem):
+    """bfc_validate: host-side checks of the problem's layout; raises on a violation."""
+    _check(_lib.load().bfc_validate(p.handle), "bfc_validate")
+
+
+def debug_fail_allocation_after(count: int) -> int:
+    """bfc_debug_fail_allocation_after: make the library's (count+1)-th next
+    device allocation fail (count < 0: off); returns the previous setting."""
+    return int(_lib.load().bfc_debug_fail_allocation_after(int(count)))
+
+
 def use_graphs(p: Problem, enable: bool = True):
     """bfc_use_graphs: replay bfc_sweep from a captured HIP graph (default on)."""
     _check(_lib.load().bfc_use_graphs(p.handle, 1 if enable else 0), "bfc_use_graphs")

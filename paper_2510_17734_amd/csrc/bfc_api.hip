@@ -1,4 +1,5 @@
 // extern "C" entry points of libbfc (declared in include/bfc.h).
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -16,8 +17,31 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+namespace {
+// allocations that still succeed before one is made to fail; < 0: off
+std::atomic<int64_t> g_fail_after{-1};
+}
+
+hipError_t lib_malloc(void** ptr, size_t bytes) {
+  int64_t k = g_fail_after.load();
+  while (k >= 0) {
+    if (g_fail_after.compare_exchange_weak(k, k - 1)) {
+      if (k == 0) {  // this one fails, as if the device were out of memory
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+      }
+      break;
+    }
+  }
+  return hipMalloc(ptr, bytes);
+}
+
+int64_t debug_fail_allocation_after(int64_t count) {
+  return g_fail_after.exchange(count < 0 ? -1 : count);
+}
+
 bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes) {
-  hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+  hipError_t e = lib_malloc(ptr, bytes ? bytes : 16);
   if (e != hipSuccess) {
     *ptr = nullptr;
     set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -31,6 +55,7 @@ bfc_status dev_free(Problem* P, void* ptr) {
   for (size_t k = 0; k < P->allocs.size(); ++k)
     if (P->allocs[k] == ptr) {
       P->allocs.erase(P->allocs.begin() + k);
+      BFC_HIP_TRY(hipDeviceSynchronize());  // no kernel may still use it
       BFC_HIP_TRY(hipFree(ptr));
       return BFC_OK;
     }
@@ -80,6 +105,7 @@ static void release_events(Profiler& pr) {
 }
 
 static void free_problem(bfc_problem* P) {
+  (void)hipDeviceSynchronize();  // work enqueued before a failure may still use the buffers
   release_events(P->prof);
   if (P->sweep_exec) (void)hipGraphExecDestroy(P->sweep_exec);
   if (P->sweep_graph) (void)hipGraphDestroy(P->sweep_graph);
@@ -289,9 +315,18 @@ bfc_status bfc_adam_sweep(bfc_problem* p, int32_t t, double alpha, double beta1,
   }
   hipStream_t st = (hipStream_t)hip_stream;
   const size_t real = p->elem / 2;
-  if (!p->adam_m) {
-    BFC_TRY(dev_alloc(p, &p->adam_m, (size_t)p->nparams * p->elem));
-    BFC_TRY(dev_alloc(p, &p->adam_v, (size_t)p->nparams * real));
+  if (!p->adam_m || !p->adam_v) {  // both moments or neither
+    void *m = nullptr, *v = nullptr;
+    BFC_TRY(dev_alloc(p, &m, (size_t)p->nparams * p->elem));
+    const bfc_status sv = dev_alloc(p, &v, (size_t)p->nparams * real);
+    if (sv != BFC_OK) {
+      (void)dev_free(p, m);
+      return sv;
+    }
+    if (p->adam_m) (void)dev_free(p, p->adam_m);
+    if (p->adam_v) (void)dev_free(p, p->adam_v);
+    p->adam_m = m;
+    p->adam_v = v;
     BFC_HIP_TRY(hipMemsetAsync(p->adam_m, 0, (size_t)p->nparams * p->elem, st));
     BFC_HIP_TRY(hipMemsetAsync(p->adam_v, 0, (size_t)p->nparams * real, st));
   }
@@ -691,7 +726,7 @@ bfc_status bfc_batch_create(bfc_problem* const* problems, int32_t count, bfc_bat
   B->prec = problems[0]->prec;
   for (int32_t k = 0; k < count; ++k) B->probs.push_back(problems[k]);
   bfc_status s = BFC_OK;
-  if (hipMalloc((void**)&B->res, 2 * sizeof(double) * count) != hipSuccess ||
+  if (lib_malloc((void**)&B->res, 2 * sizeof(double) * count) != hipSuccess ||
       hipHostMalloc((void**)&B->res_host, 2 * sizeof(double) * count, hipHostMallocDefault) !=
           hipSuccess) {
     if (B->res) (void)hipFree(B->res);
@@ -803,25 +838,58 @@ bfc_status bfc_set_item_size(bfc_problem* p, int32_t subgroups, void* hip_stream
   }
   hipStream_t st = (hipStream_t)hip_stream;
   BFC_HIP_TRY(hipStreamSynchronize(st));
-  p->item_size = subgroups;
+  // every core's new items planned on the host, every buffer that must grow
+  // allocated, and only then the problem changed: a failed allocation leaves
+  // it as it was
+  const int L = p->L;
+  std::vector<std::vector<WorkItem>> items(L + 1);
+  std::vector<std::vector<int32_t>> tiles(L + 1);
   int32_t max_items = 0;
-  for (int q = 1; q <= p->L; ++q) {
-    BFC_TRY(build_items(p, q, st));
-    max_items = std::max(max_items, p->lay[q].nitems);
+  for (int q = 1; q <= L; ++q) {
+    plan_items(p, q, subgroups, items[q], tiles[q]);
+    max_items = std::max(max_items, (int32_t)items[q].size());
   }
-  if (max_items > p->max_items) {
-    // grow the per-item buffers; their old contents are scratch
+  std::vector<void*> fresh(L + 1, nullptr);
+  void *partials = nullptr, *ir_part = nullptr;
+  bfc_status s = BFC_OK;
+  for (int q = 1; q <= L && s == BFC_OK; ++q)
+    if ((int64_t)items[q].size() > p->lay[q].items_cap || !p->lay[q].items)
+      s = dev_alloc(p, &fresh[q], std::max<size_t>(1, items[q].size()) * sizeof(WorkItem));
+  const bool grow = max_items > p->max_items;
+  if (s == BFC_OK && grow) {
+    s = dev_alloc(p, &partials, (size_t)max_items * inner_partial_bytes(p->prec, p->r));
+    if (s == BFC_OK && p->ir_part)
+      s = dev_alloc(p, &ir_part, (size_t)max_items * 2 * p->r * p->r * sizeof(float));
+  }
+  if (s != BFC_OK) {
+    const std::string msg = bfc_last_error();
+    for (void* f : fresh)
+      if (f) (void)dev_free(p, f);
+    if (partials) (void)dev_free(p, partials);
+    if (ir_part) (void)dev_free(p, ir_part);
+    set_error(msg);
+    return s;
+  }
+  for (int q = 1; q <= L; ++q) {
+    CoreLayout& C = p->lay[q];
+    if (fresh[q]) {
+      if (C.items) BFC_TRY(dev_free(p, C.items));
+      C.items = (WorkItem*)fresh[q];
+      C.items_cap = (int32_t)std::max<size_t>(1, items[q].size());
+    }
+    BFC_TRY(install_items(p, q, items[q], tiles[q], st));
+  }
+  if (grow) {
     p->max_items = max_items;
     if (p->partials) BFC_TRY(dev_free(p, p->partials));
-    p->partials = nullptr;
+    p->partials = partials;
     p->partials_bytes = (size_t)max_items * inner_partial_bytes(p->prec, p->r);
-    BFC_TRY(dev_alloc(p, &p->partials, p->partials_bytes));
-    if (p->ir_part) {
+    if (ir_part) {
       BFC_TRY(dev_free(p, p->ir_part));
-      p->ir_part = nullptr;
-      BFC_TRY(dev_alloc(p, &p->ir_part, (size_t)max_items * 2 * p->r * p->r * sizeof(float)));
+      p->ir_part = ir_part;
     }
   }
+  p->item_size = subgroups;
   // the captured sweep holds the old launch shapes and buffers
   if (p->sweep_exec) (void)hipGraphExecDestroy(p->sweep_exec);
   if (p->sweep_graph) (void)hipGraphDestroy(p->sweep_graph);
@@ -863,7 +931,7 @@ bfc_status bfc_autotune_item_size(bfc_problem* const* problems, int32_t count, i
       return BFC_EINVAL;
     }
     const size_t bytes = (size_t)P->nparams * P->elem;
-    if (hipMalloc(&saved[k], bytes) != hipSuccess) {
+    if (lib_malloc(&saved[k], bytes) != hipSuccess) {
       saved[k] = nullptr;
       release();
       set_error("autotune: no memory for the core copies");

@@ -190,6 +190,10 @@ struct Problem {
 };
 
 bfc_status dev_alloc(Problem* P, void** ptr, size_t bytes);
+// Every device allocation of the library goes through lib_malloc, so that the
+// out-of-memory paths can be exercised (bfc_debug_fail_allocation_after).
+hipError_t lib_malloc(void** ptr, size_t bytes);
+int64_t debug_fail_allocation_after(int64_t count);
 
 // One launch of a batched sweep: a kernel kind at one rank, over tasks (one
 // per problem taking part) whose argument structs and block prefix table live
@@ -239,6 +243,10 @@ bfc_status launch_set_values(Problem* P, const void* d_vals, hipStream_t st);
 bfc_status launch_cores_from_f32(Problem* P, const float* src, hipStream_t st);
 bfc_status launch_loss_gradient(Problem* P, float scale, void* out, int out_fp64, hipStream_t st);
 bfc_status build_items(Problem* P, int core, hipStream_t st);
+void plan_items(const Problem* P, int core, int32_t item_size, std::vector<WorkItem>& items,
+                std::vector<int32_t>& tile_items);
+bfc_status install_items(Problem* P, int core, const std::vector<WorkItem>& items,
+                         const std::vector<int32_t>& tile_items, hipStream_t st);
 bfc_status dev_free(Problem* P, void* ptr);
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
                           void* out, hipStream_t st);

@@ -180,10 +180,11 @@ int bits_for(uint64_t maxval) {
 struct Scratch {
   std::vector<void*> ptrs;
   ~Scratch() {
+    if (!ptrs.empty()) (void)hipDeviceSynchronize();  // after a failure, work may still run
     for (void* p : ptrs) (void)hipFree(p);
   }
   hipError_t get(void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    hipError_t e = lib_malloc(p, bytes ? bytes : 16);
     if (e == hipSuccess) ptrs.push_back(*p);
     return e;
   }
@@ -191,18 +192,19 @@ struct Scratch {
 
 }  // namespace
 
-// Work items of inner core p: chunks of P->item_size subgroups (automatic
+// Work items of inner core p: chunks of `item_size` subgroups (automatic
 // when 0: at least 128 and enough to keep the item count near 16384), never
-// across slices.  Reuses the items array while it is large enough.
-bfc_status build_items(Problem* P, int p, hipStream_t st) {
-  CoreLayout& C = P->lay[p];
-  int64_t ch = P->item_size;
+// across slices.
+void plan_items(const Problem* P, int p, int32_t item_size, std::vector<WorkItem>& items,
+                std::vector<int32_t>& tile_items) {
+  const CoreLayout& C = P->lay[p];
+  int64_t ch = item_size;
   if (ch <= 0) {
     const int64_t per_item_target = (int64_t)C.nsub / 16384 + 1;
     ch = std::max<int64_t>(128, ((per_item_target + 63) / 64) * 64);
   }
-  std::vector<WorkItem> items;
-  std::vector<int32_t> tile_items(C.nblocks + 1);
+  items.clear();
+  tile_items.assign(C.nblocks + 1, 0);
   const std::vector<int32_t>& hts = C.tile_sub;
   for (int b = 0; b < C.nblocks; ++b) {
     tile_items[b] = (int32_t)items.size();
@@ -210,12 +212,12 @@ bfc_status build_items(Problem* P, int p, hipStream_t st) {
       items.push_back({b, (int32_t)s, (int32_t)std::min<int64_t>(s + ch, hts[b + 1]), 0});
   }
   tile_items[C.nblocks] = (int32_t)items.size();
-  if ((int64_t)items.size() > C.items_cap || !C.items) {
-    if (C.items) BFC_TRY(dev_free(P, C.items));
-    C.items = nullptr;
-    C.items_cap = (int32_t)std::max<size_t>(1, items.size());
-    BFC_TRY(dev_alloc(P, (void**)&C.items, (size_t)C.items_cap * sizeof(WorkItem)));
-  }
+}
+
+// Copies planned items into core p's arrays (the items array must hold them).
+bfc_status install_items(Problem* P, int p, const std::vector<WorkItem>& items,
+                         const std::vector<int32_t>& tile_items, hipStream_t st) {
+  CoreLayout& C = P->lay[p];
   C.nitems = (int32_t)items.size();
   if (!items.empty())
     BFC_HIP_TRY(hipMemcpyAsync(C.items, items.data(), items.size() * sizeof(WorkItem),
@@ -224,6 +226,22 @@ bfc_status build_items(Problem* P, int p, hipStream_t st) {
                              hipMemcpyHostToDevice, st));
   BFC_HIP_TRY(hipStreamSynchronize(st));
   return BFC_OK;
+}
+
+// The items of inner core p at the problem's item size, at layout build.
+bfc_status build_items(Problem* P, int p, hipStream_t st) {
+  CoreLayout& C = P->lay[p];
+  std::vector<WorkItem> items;
+  std::vector<int32_t> tile_items;
+  plan_items(P, p, P->item_size, items, tile_items);
+  if ((int64_t)items.size() > C.items_cap || !C.items) {
+    void* fresh = nullptr;
+    BFC_TRY(dev_alloc(P, &fresh, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
+    if (C.items) BFC_TRY(dev_free(P, C.items));
+    C.items = (WorkItem*)fresh;
+    C.items_cap = (int32_t)std::max<size_t>(1, items.size());
+  }
+  return install_items(P, p, items, tile_items, st);
 }
 
 bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols,

@@ -2370,9 +2370,9 @@ bfc_status upload_tasks(Batch* B, int kind, int r, const std::vector<A>& args,
   }
   bl.blocks = off.back();
   if (bl.blocks == 0) return BFC_OK;
-  BFC_HIP_TRY(hipMalloc(&bl.tasks, sizeof(A) * args.size()));
+  BFC_HIP_TRY(lib_malloc(&bl.tasks, sizeof(A) * args.size()));
   B->allocs.push_back(bl.tasks);
-  BFC_HIP_TRY(hipMalloc((void**)&bl.block_off, sizeof(int32_t) * off.size()));
+  BFC_HIP_TRY(lib_malloc((void**)&bl.block_off, sizeof(int32_t) * off.size()));
   B->allocs.push_back(bl.block_off);
   BFC_HIP_TRY(hipMemcpy(bl.tasks, args.data(), sizeof(A) * args.size(), hipMemcpyHostToDevice));
   BFC_HIP_TRY(hipMemcpy(bl.block_off, off.data(), sizeof(int32_t) * off.size(),

@@ -418,7 +418,7 @@ extern "C" bfc_status bfc_lowrank_to_butterfly(int64_t n, int32_t L, int32_t r, 
                       "bfc_lowrank_to_butterfly"));
   hipStream_t st = (hipStream_t)hip_stream;
   double2* buf = nullptr;
-  BFC_HIP_TRY(hipMalloc((void**)&buf, sizeof(double2) * lr2bf_scratch_elems(L, r, R, p)));
+  BFC_HIP_TRY(lib_malloc((void**)&buf, sizeof(double2) * lr2bf_scratch_elems(L, r, R, p)));
   const bfc_status status =
       lr2bf_enqueue(n, L, r, R, p, (const double2*)d_A, (const double2*)d_B,
                     (const double2*)d_sketches, (double2*)d_cores_out, buf, st);

@@ -120,3 +120,12 @@ def test_noalloc_conversion_argument_checks():
     assert f(1024, 4, 9, 6, 4, fake, fake, fake, fake, None) == _lib.BFC_EINVAL
     assert f(262144, 12, 8, 8, 4, fake, fake, fake, fake, None) == _lib.BFC_EINVAL
     assert "maximum" in lib.bfc_last_error().decode()
+
+
+def test_debug_entry_points_without_a_problem():
+    lib = _lib.load()
+    assert lib.bfc_validate(None) == _lib.BFC_EINVAL
+    assert "null" in lib.bfc_last_error().decode()
+    prev = lib.bfc_debug_fail_allocation_after(5)
+    assert lib.bfc_debug_fail_allocation_after(-1) == 5
+    assert lib.bfc_debug_fail_allocation_after(prev) == -1
