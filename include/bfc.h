@@ -91,7 +91,16 @@ typedef int32_t bfc_status;
 #define BFC_REG_PROXIMAL 0
 #define BFC_REG_RIDGE 1
 
-#define BFC_MAX_RANK 8
+/* Ranks: the ALS sweep (bfc_sweep_core, bfc_sweep), reconstruction and the
+ * residual calls take 1 <= r <= BFC_MAX_RANK.  Every other call (ADAM, ADF,
+ * the loss gradient, batches, work-item sizes, the low-rank conversion) and
+ * the BFC_C64_BF16GRAM mode need r <= BFC_MAX_RANK_FULL and return EINVAL
+ * above it.  From r = BFC_MAX_RANK_FULL + 1 (the ranks 10 - 12 of the c = 4
+ * examples of Sec. 6.1 and 6.3) an inner slice's system (d = r^2 unknowns)
+ * is built and solved by one fused kernel per slice, with a region of
+ * device memory of its own for the real Gram and the factor.             */
+#define BFC_MAX_RANK 12
+#define BFC_MAX_RANK_FULL 8
 #define BFC_MAX_LEVELS 24
 
 typedef struct bfc_config {

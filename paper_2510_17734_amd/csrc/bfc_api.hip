@@ -126,7 +126,11 @@ static bfc_status check_config(const bfc_config* cfg, int32_t* c_out) {
     return BFC_EINVAL;
   }
   if (cfg->r < 1 || cfg->r > BFC_MAX_RANK) {
-    set_error("r out of range [1, 8]");
+    set_error("r out of range [1, 12]");
+    return BFC_EINVAL;
+  }
+  if (cfg->r > BFC_MAX_RANK_FULL && cfg->precision == BFC_C64_BF16GRAM) {
+    set_error("the BF16-Gram mode supports r <= 8");
     return BFC_EINVAL;
   }
   const int64_t two_l = (int64_t)1 << cfg->L;
@@ -313,6 +317,10 @@ bfc_status bfc_adam_sweep(bfc_problem* p, int32_t t, double alpha, double beta1,
     set_error("bfc_adam_sweep: need t >= 1, alpha > 0, 0 <= beta1, beta2 < 1, sigma >= 0");
     return BFC_EINVAL;
   }
+  if (p->r > BFC_MAX_RANK_FULL) {
+    set_error("bfc_adam_sweep: supports r <= 8");
+    return BFC_EINVAL;
+  }
   hipStream_t st = (hipStream_t)hip_stream;
   const size_t real = p->elem / 2;
   if (!p->adam_m || !p->adam_v) {  // both moments or neither
@@ -345,6 +353,10 @@ bfc_status bfc_adam_sweep(bfc_problem* p, int32_t t, double alpha, double beta1,
 bfc_status bfc_adf_sweep(bfc_problem* p, void* hip_stream) {
   if (!p) {
     set_error("null problem");
+    return BFC_EINVAL;
+  }
+  if (p->r > BFC_MAX_RANK_FULL) {
+    set_error("bfc_adf_sweep: supports r <= 8");
     return BFC_EINVAL;
   }
   if (p->c > 64 || p->c < p->r) {
@@ -518,6 +530,10 @@ bfc_status bfc_loss_gradient(bfc_problem* p, float scale, void* d_grad, int32_t 
                              double* loss, void* hip_stream) {
   if (!p || !d_grad || !(scale == scale)) {
     set_error("bad loss_gradient arguments");
+    return BFC_EINVAL;
+  }
+  if (p->r > BFC_MAX_RANK_FULL) {
+    set_error("bfc_loss_gradient: supports r <= 8");
     return BFC_EINVAL;
   }
   hipStream_t st = (hipStream_t)hip_stream;
@@ -709,6 +725,10 @@ bfc_status bfc_batch_create(bfc_problem* const* problems, int32_t count, bfc_bat
         set_error("a problem appears twice in the batch");
         return BFC_EINVAL;
       }
+    if (problems[k]->r > BFC_MAX_RANK_FULL) {
+      set_error("bfc_batch_create: batches support r <= 8");
+      return BFC_EINVAL;
+    }
     if (problems[k]->prec != problems[0]->prec) {
       set_error("problems of one batch must share the arithmetic mode");
       return BFC_EINVAL;
@@ -834,6 +854,10 @@ bfc_status bfc_batch_destroy(bfc_batch* b) {
 bfc_status bfc_set_item_size(bfc_problem* p, int32_t subgroups, void* hip_stream) {
   if (!p || subgroups < 0 || subgroups > 65536 || subgroups % 64 != 0) {
     set_error("item size must be 0 (automatic) or a multiple of 64 in [64, 65536]");
+    return BFC_EINVAL;
+  }
+  if (p->r > BFC_MAX_RANK_FULL) {
+    set_error("bfc_set_item_size (one work item per slice above r = 8): supports r <= 8");
     return BFC_EINVAL;
   }
   hipStream_t st = (hipStream_t)hip_stream;

@@ -72,6 +72,12 @@ __host__ __device__ inline void cfma_conj(cx<T>& acc, cx<T> a, cx<T> b) {
 // pieces of at most this many entries, one lane each in the Gram kernel.
 constexpr int kSubgroup = 8;
 
+// Highest rank of the one-wavefront kernels and of every call of the library;
+// ranks kNarrowRank+1 .. BFC_MAX_RANK have the sweep, reconstruction and
+// residual calls only (fused per-slice kernels, one work item per slice).
+constexpr int kNarrowRank = 8;
+static_assert(kNarrowRank == BFC_MAX_RANK_FULL, "narrow kernel range");
+
 struct WorkItem {   // a run of subgroups of one inner-core slice, one wavefront
   int32_t tile, sub0, sub1, pad;
 };

@@ -175,6 +175,31 @@ __host__ __device__ inline void herm_coord(int a, int b, int R, int& re, int& im
   }
 }
 
+// K[(a,b),(a2,b2)] of an inner slice from S (row-major, width W):
+// K = sum (Hl[a][a2] * Hr[b][b2]) with Hl, Hr given by their real coordinates.
+template <int R>
+__device__ inline double2 inner_K(const double* S, int W, int row, int col) {
+  const int a = row / R, b = row % R, a2 = col / R, b2 = col % R;
+  int reA, imA, sA, reB, imB, sB;
+  herm_coord(a, a2, R, reA, imA, sA);
+  herm_coord(b, b2, R, reB, imB, sB);
+  double re = S[reA * W + reB];
+  double im = 0.0;
+  if (imA >= 0 && imB >= 0) re -= (double)(sA * sB) * S[imA * W + imB];
+  if (imB >= 0) im += (double)sB * S[reA * W + imB];
+  if (imA >= 0) im += (double)sA * S[imA * W + reB];
+  return make_double2(re, im);
+}
+
+// right-hand side h[(a,b)] from the 2r x 2r corner of S
+template <int R>
+__device__ inline double2 inner_h(const double* S, int W, int row) {
+  const int a = row / R, b = row % R;
+  const int D = R * R;
+  const int Are = D + a, Aim = D + R + a, Bre = D + b, Bim = D + R + b;
+  return make_double2(S[Are * W + Bre] + S[Aim * W + Bim], S[Are * W + Bim] - S[Aim * W + Bre]);
+}
+
 // MFMA wrappers: D(16x16) += X(16x4) Y(4x16); lane l supplies X[l%16][l/16]
 // and Y[l/16][l%16].  Element v of the accumulator holds D[out_row][l%16];
 // the row mapping differs between the FP32 and the FP64 instruction (both
@@ -563,6 +588,121 @@ __device__ inline T wave_sum(T v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// ---------------------------------------------------------------------------
+// Hermitian positive definite solve with the matrix in registers.
+//
+// The (D+1) x (D+1) bordered matrix [[K, .], [conj(b)^T, .]] (K Hermitian,
+// D x D; only entries on or below the diagonal are held, the last row being
+// the conjugated right-hand side) is distributed 2D block-cyclically over a
+// G x G grid of threads: thread (a, c) holds entry (i, j) = (a + G ia,
+// c + G jc) in (mr, mi)[ia][jc] (ia >= jc; slots with i < j are carried but
+// never read).  The Cholesky factorization [[K, b], [b^H, *]] = [[L, 0], [w^H, *]]
+// [[L^H, w], [0, *]] leaves L in place of K and conj(w) = conj(L^-1 b) in
+// the last row, so the forward substitution rides along.
+// ---------------------------------------------------------------------------
+template <int D, int G>
+struct RegGrid {
+  static constexpr int D1 = D + 1;                 // rows, the border included
+  static constexpr int NS = (D1 + G - 1) / G;      // slot rows (and columns) per thread
+};
+
+// Orders the LDS traffic of the threads of one grid: a wavefront fence when
+// the grid is one wavefront, a workgroup barrier otherwise.
+template <int G>
+__device__ __attribute__((always_inline)) inline void grid_sync() {
+  if constexpr (G * G <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Right-looking factorization, one column at a time, one sync per column.
+// The owners of column k publish it (unscaled) to col (two buffers of D+1
+// values, used alternately) and every thread reads it back with the pivot
+// p = a_kk; every thread then updates its trailing entries
+// a_ij -= a_ik conj(a_jk) / p (i, j > k), and the owners of column k scale
+// it (l_kk = sqrt(p), l_ik = a_ik / sqrt(p)).  The pivot is read by every
+// thread from the same LDS value, so a pivot that is not positive makes
+// every thread return false at the same column.
+// Columns KB*G .. KB*G+G-1 (slot column KB of every thread); a template per
+// slot column, so every slot index is a constant and the slots stay in
+// registers (real and imaginary parts in plain double arrays: a struct array
+// with union members is not split into registers).  The row factor a_ik / p
+// is read per slot row inside the update, so only the column factors of the
+// thread's slot columns are held.
+template <int D, int G, int NS, int KB>
+__device__ __attribute__((always_inline)) inline bool reg_cholesky_cols(double (&mr)[NS][NS],
+                                                                        double (&mi)[NS][NS],
+                                                                        int a, int c,
+                                                                        double2* col) {
+  if constexpr (KB >= NS) {
+    return true;
+  } else {
+    constexpr int D1 = D + 1;
+#pragma unroll 1
+    for (int kk = 0; kk < G; ++kk) {
+      const int k = KB * G + kk;
+      if (k >= D) break;
+      double2* buf = col + (k & 1) * D1;
+      if (c == kk) {
+#pragma unroll
+        for (int ia = KB; ia < NS; ++ia) {
+          const int i = a + G * ia;
+          if (i >= k && i <= D) buf[i] = make_double2(mr[ia][KB], mi[ia][KB]);
+        }
+      }
+      grid_sync<G>();
+      const double p = buf[k].x;
+      if (!(p > 0.0)) return false;
+      const double rs = rsqrt_nr(p), inv = rs * rs;
+      double cjr[NS], cji[NS];
+#pragma unroll
+      for (int q = KB; q < NS; ++q) {
+        const int j = c + G * q;
+        const double2 v = (j > k && j < D) ? buf[j] : make_double2(0.0, 0.0);
+        cjr[q] = v.x;
+        cji[q] = v.y;
+      }
+#pragma unroll
+      for (int ia = KB; ia < NS; ++ia) {
+        const int i = a + G * ia;
+        const double2 u = (i > k && i <= D) ? buf[i] : make_double2(0.0, 0.0);
+        const double cr = u.x * inv, ci = u.y * inv;
+#pragma unroll
+        for (int jc = KB; jc <= ia; ++jc) {
+          mr[ia][jc] -= cr * cjr[jc] + ci * cji[jc];
+          mi[ia][jc] -= ci * cjr[jc] - cr * cji[jc];
+        }
+      }
+      if (c == kk) {
+#pragma unroll
+        for (int ia = KB; ia < NS; ++ia) {
+          const int i = a + G * ia;
+          if (i == k) {
+            mr[ia][KB] = p * rs;
+            mi[ia][KB] = 0.0;
+          } else if (i > k && i <= D) {
+            mr[ia][KB] *= rs;
+            mi[ia][KB] *= rs;
+          }
+        }
+      }
+    }
+    return reg_cholesky_cols<D, G, NS, KB + 1>(mr, mi, a, c, col);
+  }
+}
+
+template <int D, int G, int NS>
+__device__ __attribute__((always_inline)) inline bool reg_cholesky(double (&mr)[NS][NS],
+                                                                   double (&mi)[NS][NS], int a,
+                                                                   int c, double2* col) {
+  static_assert(NS == RegGrid<D, G>::NS, "slot count of the grid");
+  return reg_cholesky_cols<D, G, NS, 0>(mr, mi, a, c, col);
 }
 
 }  // namespace bfc

@@ -199,7 +199,9 @@ void plan_items(const Problem* P, int p, int32_t item_size, std::vector<WorkItem
                 std::vector<int32_t>& tile_items) {
   const CoreLayout& C = P->lay[p];
   int64_t ch = item_size;
-  if (ch <= 0) {
+  if (P->r > kNarrowRank) {
+    ch = INT32_MAX;  // the fused kernels of the wide ranks: one item per slice
+  } else if (ch <= 0) {
     const int64_t per_item_target = (int64_t)C.nsub / 16384 + 1;
     ch = std::max<int64_t>(128, ((per_item_target + 63) / 64) * 64);
   }

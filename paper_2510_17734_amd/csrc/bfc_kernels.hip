@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "bfc_device.h"
+#include "bfc_wide.h"
 
 namespace bfc {
 
@@ -149,31 +150,6 @@ __global__ __launch_bounds__(kResThreads) void residual_final_batched(const ResF
 // ---------------------------------------------------------------------------
 // Hermitian system assembly from real coordinates
 // ---------------------------------------------------------------------------
-
-// K[(a,b),(a2,b2)] of an inner slice from S (row-major, width W):
-// K = sum (Hl[a][a2] * Hr[b][b2]) with Hl, Hr given by their real coordinates.
-template <int R>
-__device__ inline double2 inner_K(const double* S, int W, int row, int col) {
-  const int a = row / R, b = row % R, a2 = col / R, b2 = col % R;
-  int reA, imA, sA, reB, imB, sB;
-  herm_coord(a, a2, R, reA, imA, sA);
-  herm_coord(b, b2, R, reB, imB, sB);
-  double re = S[reA * W + reB];
-  double im = 0.0;
-  if (imA >= 0 && imB >= 0) re -= (double)(sA * sB) * S[imA * W + imB];
-  if (imB >= 0) im += (double)sB * S[reA * W + imB];
-  if (imA >= 0) im += (double)sA * S[imA * W + reB];
-  return make_double2(re, im);
-}
-
-// right-hand side h[(a,b)] from the 2r x 2r corner of S
-template <int R>
-__device__ inline double2 inner_h(const double* S, int W, int row) {
-  const int a = row / R, b = row % R;
-  const int D = R * R;
-  const int Are = D + a, Aim = D + R + a, Bre = D + b, Bim = D + R + b;
-  return make_double2(S[Are * W + Bre] + S[Aim * W + Bim], S[Are * W + Bim] - S[Aim * W + Bre]);
-}
 
 // ---------------------------------------------------------------------------
 // outer cores: 16 lanes (one DPP row) per fiber, fused serial solve
@@ -1461,6 +1437,45 @@ bfc_status ensure_left(Problem* P, int p, hipStream_t st) {
 }
 
 template <typename T, int R>
+bfc_status sweep_core_wide(Problem* P, int p, hipStream_t st) {
+  cx<T>* cores = (cx<T>*)P->cores;
+  const CoreLayout& C = P->lay[p];
+  const int L = P->L;
+  const double reg = P->cfg.reg_rel;
+  const double floor_ = reg_floor_of(P);
+  const int prox = P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0;
+  {
+    ProfScope ps(&P->prof, KIND_ENV, st);
+    BFC_TRY(ensure_right<T, R>(P, p, st));
+    BFC_TRY(ensure_left<T, R>(P, p, st));
+  }
+  const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R)
+                               : (p <= L - 1 ? (const cx<T>*)P->rlev[p].vec : nullptr);
+  const int32_t* ridx = (p == L) ? C.cols : C.rnode;
+  const cx<T>* lenv = (p == 1) ? cores : (p >= 2 ? (const cx<T>*)P->llev[p].vec : nullptr);
+  const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
+  if (p == 0 || p == L + 1) {
+    cx<T>* fibers = cores + (p == 0 ? 0 : last_off(P->n, L, R));
+    ProfScope ps(&P->prof, KIND_OUTER, st);
+    BFC_TRY(launch_outer_wide<T, R>(
+        WideOuterArgs<T>{fibers, p == 0 ? renv : lenv, p == 0 ? ridx : lidx,
+                         (const cx<T>*)C.vals, C.blk_off, C.nblocks, reg, floor_, prox, P->flags},
+        st));
+  } else if (C.nitems > 0) {
+    ProfScope ps(&P->prof, KIND_INNER_GRAM, st);
+    const WideArgs<T> a{cores + inner_off(P->n, L, R, p), lenv, lidx, renv, ridx,
+                        (const cx<T>*)C.vals, C.sub_off, C.items, C.tile_items,
+                        (unsigned char*)P->partials, reg, floor_, prox, P->flags};
+    BFC_TRY(launch_inner_wide<T, R>(a, C.nblocks, C.group_by_row, st));
+  }
+  P->fused_res_valid = false;
+  for (int q = 0; q < p && q < L; ++q) P->rlev[q].valid = false;
+  for (int q = p + 1; q <= L + 1; ++q)
+    if (q >= 2) P->llev[q].valid = false;
+  return BFC_OK;
+}
+
+template <typename T, int R>
 bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   cx<T>* cores = (cx<T>*)P->cores;
   const CoreLayout& C = P->lay[p];
@@ -2286,11 +2301,14 @@ bfc_status residual_t(const Problem* P, int64_t m, const int32_t* rows, const in
   return BFC_OK;
 }
 
-template <template <typename, int> class F, typename... Args>
-bfc_status dispatch(int prec, int r, Args... args) {
 #define BFC_CASE(RR)                                                     \
   case RR:                                                               \
     return prec == BFC_C128 ? F<double, RR>::run(args...) : F<float, RR>::run(args...);
+
+// Calls that exist at ranks 1 .. kNarrowRank only (ADAM, ADF, the loss
+// gradient): instantiated for those ranks.
+template <template <typename, int> class F, typename... Args>
+bfc_status dispatch(int prec, int r, Args... args) {
   switch (r) {
     BFC_CASE(1)
     BFC_CASE(2)
@@ -2301,15 +2319,42 @@ bfc_status dispatch(int prec, int r, Args... args) {
     BFC_CASE(7)
     BFC_CASE(8)
     default:
+      set_error("this call supports ranks 1 .. 8");
+      return BFC_EINVAL;
+  }
+}
+
+// The ALS sweep, reconstruction and residuals: every rank up to BFC_MAX_RANK.
+template <template <typename, int> class F, typename... Args>
+bfc_status dispatch_any(int prec, int r, Args... args) {
+  switch (r) {
+    BFC_CASE(1)
+    BFC_CASE(2)
+    BFC_CASE(3)
+    BFC_CASE(4)
+    BFC_CASE(5)
+    BFC_CASE(6)
+    BFC_CASE(7)
+    BFC_CASE(8)
+    BFC_CASE(9)
+    BFC_CASE(10)
+    BFC_CASE(11)
+    BFC_CASE(12)
+    default:
       set_error("rank out of range");
       return BFC_EINVAL;
   }
-#undef BFC_CASE
 }
+#undef BFC_CASE
 
 template <typename T, int R>
 struct SweepF {
-  static bfc_status run(Problem* P, int p, hipStream_t st) { return sweep_core_t<T, R>(P, p, st); }
+  static bfc_status run(Problem* P, int p, hipStream_t st) {
+    if constexpr (R > kNarrowRank)
+      return sweep_core_wide<T, R>(P, p, st);
+    else
+      return sweep_core_t<T, R>(P, p, st);
+  }
 };
 template <typename T, int R>
 struct AdamF {
@@ -2635,13 +2680,14 @@ size_t inner_factor_bytes(int r) {
 }
 
 size_t inner_partial_bytes(int prec, int r) {
+  if (r > kNarrowRank) return wide_region_bytes(r);  // the fused kernels' per-slice region
   const int W = r * r + 2 * r;
   const int WP = (W + 15) / 16 * 16;
   return (size_t)WP * WP * (prec == BFC_C128 ? 8 : 4);
 }
 
 bfc_status launch_sweep_core(Problem* P, int core, hipStream_t st) {
-  return dispatch<SweepF>(P->prec, P->r, P, core, st);
+  return dispatch_any<SweepF>(P->prec, P->r, P, core, st);
 }
 
 bfc_status launch_adam_core(Problem* P, int core, int t, double alpha, double beta1,
@@ -2658,16 +2704,16 @@ bfc_status launch_adf_sweep(Problem* P, hipStream_t st) {
 bfc_status launch_predict(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
                           void* out, hipStream_t st) {
   if (m == 0) return BFC_OK;
-  return dispatch<PredictF>(P->prec, P->r, P, m, rows, cols, out, st);
+  return dispatch_any<PredictF>(P->prec, P->r, P, m, rows, cols, out, st);
 }
 
 bfc_status launch_residual(const Problem* P, int64_t m, const int32_t* rows, const int32_t* cols,
                            const void* vals, double* out2, hipStream_t st) {
-  return dispatch<ResidualF>(P->prec, P->r, P, m, rows, cols, vals, out2, st);
+  return dispatch_any<ResidualF>(P->prec, P->r, P, m, rows, cols, vals, out2, st);
 }
 
 bfc_status launch_residual_observed(Problem* P, double* out2, hipStream_t st) {
-  return dispatch<ResidualObservedF>(P->prec, P->r, P, out2, st);
+  return dispatch_any<ResidualObservedF>(P->prec, P->r, P, out2, st);
 }
 
 void invalidate_envs(Problem* P) {

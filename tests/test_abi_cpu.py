@@ -55,7 +55,9 @@ def _init(cfg, nnz=10, rows=1, cols=1, vals=1):
 @pytest.mark.parametrize("cfg,why", [
     (None, "null config"),
     (_lib.BfcConfig(256, 4, 0, 0, 0, 1e-10, 0), "r"),
-    (_lib.BfcConfig(256, 4, 9, 0, 0, 1e-10, 0), "r"),
+    (_lib.BfcConfig(256, 4, 13, 0, 0, 1e-10, 0), "r"),
+    # ranks above 8 exist for the complex128 / complex64 sweeps only
+    (_lib.BfcConfig(256, 4, 9, _lib.BFC_C64_BF16GRAM, 0, 1e-10, 0), "BF16-Gram"),
     (_lib.BfcConfig(250, 4, 4, 0, 0, 1e-10, 0), "n"),
     (_lib.BfcConfig(256, -1, 4, 0, 0, 1e-10, 0), "L"),
     (_lib.BfcConfig(256, 4, 4, 7, 0, 1e-10, 0), "precision"),

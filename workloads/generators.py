@@ -216,6 +216,15 @@ WORKLOADS = {
     "green-planes-4096-c4": (4096, 10, 8, 64 * math.pi / 5, "planes", 66, 10000, 6),
     "green-planes-16384-c4": (16384, 12, 8, 128 * math.pi / 5, "planes", 48, 10000, 7),
     "radon-256": (256, 6, 4, 0.0, "radon", 30, 1000, 5),
+    # the same examples at the paper's ranks.  Radon (Sec. 6.3): n = 1024 at
+    # r = 10 with 30 n log2 n entries; n = 4096 at r = 12 with the printed
+    # counts 3,440,640 training (= 70 n log2 n) and 491,520 test entries.
+    # Green's grids (Sec. 6.1): n = 4096 at r = 11 with 66 n log2 n entries;
+    # n = 16384 at r = 11 with 6 r n log2 n = 15,138,816 entries.
+    "radon-1024-r10": (1024, 8, 10, 0.0, "radon", 30, 10000, 4),
+    "radon-4096-r12": (4096, 10, 12, 0.0, "radon", 70, 491520, 8),
+    "green-planes-4096-c4-r11": (4096, 10, 11, 64 * math.pi / 5, "planes", 66, 10000, 6),
+    "green-planes-16384-c4-r11": (16384, 12, 11, 128 * math.pi / 5, "planes", 66, 10000, 7),
 }
 
 
