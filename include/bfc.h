@@ -138,7 +138,9 @@ int64_t bfc_num_params(int64_t n, int32_t L, int32_t r);
  * the FP32-accumulated Grams of the complex64 modes: the FP32 unit roundoff
  * 2^-24 times the sqrt(256) growth of the sums forming them; the same 2^-20
  * for the inner Grams of BFC_C64_BF16GRAM, whose bf16 inputs are split in
- * three bf16 parts), so that rounding cannot make K + lam I indefinite.  If
+ * three bf16 parts; 0 again for BFC_C64 at r > BFC_MAX_RANK_FULL, where the
+ * Grams are accumulated in FP64 from the complex64 values), so that
+ * rounding cannot make K + lam I indefinite.  If
  * the FP64 Cholesky factorization still fails while lam > 0, lam is raised to
  * max(100 lam, d max(u, 2^-53) tau), at most three times.
  * Returns EINVAL for nnz < 1, a bad config (n not c*2^L, r or L out of

@@ -611,7 +611,8 @@ constexpr int kBfLdk = 32 + 4;  // subgroups per staged coordinate row (one phas
 // Rounding level u of a problem's regularization floor: that of its Gram
 // accumulation, raised to the configured lower bound.
 inline double reg_floor_of(const Problem* P) {
-  const double uk = P->prec == BFC_C128 ? 0.0 : kF32RegFloor;
+  // the wide-rank kernels accumulate every Gram in FP64
+  const double uk = (P->prec == BFC_C128 || P->r > kNarrowRank) ? 0.0 : kF32RegFloor;
   return uk > P->cfg.reg_floor ? uk : P->cfg.reg_floor;
 }
 

@@ -1,6 +1,11 @@
 // ALS core updates at the wide ranks (Alg. "ALS for Butterfly Completion",
 // Sec. 5.1.1): the same normal equations, regularization and ladder as the
 // one-wavefront kernels, laid out for r^2 = 81 .. 144 unknowns per slice.
+// Both precisions form the Gram matrices in FP64 (products of the stored
+// complex64 or complex128 values, FP64 MFMA): these kernels are bound by
+// gathers and synchronization rather than by matrix throughput, and an
+// FP64 Gram needs no rounding floor in the regularization, which at
+// d = r^2 = 144 unknowns would be large (d times the floor).
 #include "bfc_device.h"
 #include "bfc_wide.h"
 
@@ -26,11 +31,16 @@ namespace {
 //   K block and the right-hand-side corner).  S goes to the slice's region
 //   of device memory (it does not fit in LDS at r = 12), the bordered system
 //   is assembled from it into registers over a 32 x 32 thread grid and
-//   factored there (reg_cholesky); the factor's rows replace S in the region
-//   and one wavefront back-substitutes.
+//   factored there (reg_cholesky); the factor's rows replace S in the region,
+//   and a second launch back-substitutes with one wavefront per slice.
 // ---------------------------------------------------------------------------
 constexpr int kWideSub = 16;       // subgroups per batch of the fused inner kernel
 constexpr int kWideThreads = 1024;  // threads of the fused inner kernel
+
+template <typename T>
+__device__ __attribute__((always_inline)) inline cx<double> widen(cx<T> v) {
+  return {(double)v.x, (double)v.y};
+}
 
 template <int R>
 struct WideGeom {
@@ -43,7 +53,10 @@ struct WideGeom {
   static constexpr int NS = RegGrid<D, G>::NS;
   static constexpr size_t S_BYTES = (size_t)WP * WP * 8;
   static constexpr size_t F_BYTES = (size_t)D * (D + 1) / 2 * 16;
-  static constexpr size_t REGION = S_BYTES > F_BYTES ? S_BYTES : F_BYTES;
+  // after the factorization: the factor's rows, then w = L^-1 (h + lam s_old)
+  // and a status value (1: factored, 0: no rung of the ladder was)
+  static constexpr size_t FW_BYTES = F_BYTES + (size_t)(D + 1) * 16;
+  static constexpr size_t REGION = S_BYTES > FW_BYTES ? S_BYTES : FW_BYTES;
 };
 
 // MFMA tile (x, y) of S is read by the system: the K block (coordinates
@@ -61,12 +74,14 @@ constexpr int wide_tiles() {
   return n;
 }
 
-// One real coordinate (index k = p R + q) of conj(v) v^T, as in herm_acc.
+// One real coordinate (index k = p R + q) of conj(v) v^T, as in herm_acc,
+// in FP64 (exact for complex64 inputs up to the one final rounding).
 template <typename T>
-__device__ __attribute__((always_inline)) inline T herm_value(const cx<T>* v, int p, int q) {
-  if (p == q) return v[p].x * v[p].x + v[p].y * v[p].y;
-  if (p < q) return v[p].x * v[q].x + v[p].y * v[q].y;
-  return v[q].x * v[p].y - v[q].y * v[p].x;
+__device__ __attribute__((always_inline)) inline double herm_value(const cx<T>* v, int p, int q) {
+  const double px = v[p].x, py = v[p].y, qx = v[q].x, qy = v[q].y;
+  if (p == q) return px * px + py * py;
+  if (p < q) return px * qx + py * qy;
+  return qx * py - qy * px;
 }
 
 // Wavefront Cholesky of the leading d x d block of M (row-major, leading
@@ -101,8 +116,8 @@ __device__ inline bool wave_cholesky_lds(double2* M, int ld, int d, int lane) {
 
 // Outer core update at ranks above the one-wavefront kernels' range: one
 // wavefront per fiber (the fiber's r unknowns, its entries blk_off[b] ..
-// blk_off[b+1]).  The Gram is accumulated in the compute precision, the
-// regularized solve is FP64, as in the narrow kernel.
+// blk_off[b+1]).  The Gram is accumulated in FP64 from the stored values in
+// both precisions, and the regularized solve is FP64.
 template <typename T, int R>
 __global__ __launch_bounds__(64) void outer_wide_kernel(WideOuterArgs<T> A) {
   constexpr int NP = R * (R + 1) / 2;  // lower-triangle entries of K
@@ -129,9 +144,9 @@ __global__ __launch_bounds__(64) void outer_wide_kernel(WideOuterArgs<T> A) {
     ji[q] = job < NP ? i : (job < NJ ? job - NP : -1);
     jj[q] = job < NP ? job - i * (i + 1) / 2 : -1;
   }
-  cx<T> acc[JL];
+  cx<double> acc[JL];  // FP64 accumulation in both precisions
 #pragma unroll
-  for (int q = 0; q < JL; ++q) acc[q] = cx<T>{T(0), T(0)};
+  for (int q = 0; q < JL; ++q) acc[q] = cx<double>{0.0, 0.0};
   for (int base = e0; base < e1; base += 64) {
     const int e = base + lane;
     if (e < e1) {
@@ -147,9 +162,9 @@ __global__ __launch_bounds__(64) void outer_wide_kernel(WideOuterArgs<T> A) {
       for (int q = 0; q < JL; ++q) {
         const int job = lane + 64 * q;
         if (job < NP)
-          cfma_conj(acc[q], vs[u][ji[q]], vs[u][jj[q]]);
+          cfma_conj(acc[q], widen(vs[u][ji[q]]), widen(vs[u][jj[q]]));
         else if (job < NJ)
-          cfma_conj(acc[q], vs[u][ji[q]], ts[u]);
+          cfma_conj(acc[q], widen(vs[u][ji[q]]), widen(ts[u]));
       }
     }
     wave_sync();
@@ -159,8 +174,8 @@ __global__ __launch_bounds__(64) void outer_wide_kernel(WideOuterArgs<T> A) {
 #pragma unroll
   for (int q = 0; q < JL; ++q) {
     const int job = lane + 64 * q;
-    kd[q][0] = (double)acc[q].x;
-    kd[q][1] = (double)acc[q].y;
+    kd[q][0] = acc[q].x;
+    kd[q][1] = acc[q].y;
     if (job >= NP && job < NJ) hv[ji[q]] = make_double2(kd[q][0], kd[q][1]);
     if (job < NP && ji[q] == jj[q]) M[ji[q] * LD + ji[q]] = make_double2(kd[q][0], 0.0);
   }
@@ -245,16 +260,15 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
   constexpr int NTILE = wide_tiles<R>(), TPW = (NTILE + NW - 1) / NW;
   static_assert(GG * GG == NT, "factorization grid");
   static_assert(kWideSub == NW, "one wavefront per subgroup of a batch");
-  typedef typename Mfma<T>::acc_t acc_t;
+  typedef Mfma<double>::acc_t acc_t;  // the Gram in FP64 in both precisions
   __shared__ cx<T> us[kWideSub][R];              // each subgroup's shared environment
   __shared__ cx<T> vs[kWideSub][kSubgroup][R];   // its entries' other environment
   __shared__ cx<T> ts[kWideSub][kSubgroup];      // its entries' values
-  __shared__ T As[kWideSub * LDW];
-  __shared__ T Bs[kWideSub * LDW];
+  __shared__ double As[kWideSub * LDW];
+  __shared__ double Bs[kWideSub * LDW];
   __shared__ double2 col[2 * (D + 1)];
   __shared__ double2 hb[D];
   __shared__ double2 ob[D];
-  __shared__ double2 ys[D];
   __shared__ double dg[D];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -282,7 +296,7 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
   }
   acc_t acc[TPW];
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) acc[q] = acc_t{T(0), T(0), T(0), T(0)};
+  for (int q = 0; q < TPW; ++q) acc[q] = acc_t{0.0, 0.0, 0.0, 0.0};
   const cx<T> zero = {T(0), T(0)};
   for (int base = s_beg; base < s_end; base += kWideSub) {
     {  // gather: wavefront `wave` takes subgroup base + wave
@@ -307,14 +321,14 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
     wave_sync();
     {  // the subgroup's rows: A = shared side, B = the sum over its entries
        // (row case; the column case swaps them and conjugates the RHS parts)
-      T* arow = As + wave * LDW;
-      T* brow = Bs + wave * LDW;
+      double* arow = As + wave * LDW;
+      double* brow = Bs + wave * LDW;
       for (int k = lane; k < WP; k += 64) {
-        T a = T(0), bv = T(0);
+        double a = 0.0, bv = 0.0;
         if (k < D) {
           const int p = k / R, q = k - p * R;
-          const T hs = herm_value<T>(us[wave], p, q);
-          T he = T(0);
+          const double hs = herm_value<T>(us[wave], p, q);
+          double he = 0.0;
 #pragma unroll
           for (int e = 0; e < kSubgroup; ++e) he += herm_value<T>(vs[wave][e], p, q);
           a = BYROW ? hs : he;
@@ -322,10 +336,10 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
         } else if (k < W) {
           const int c = (k - D) % R;
           const bool im = k - D >= R;
-          cx<T> y = zero;  // sum conj(v_e) t_e at coordinate c
+          cx<double> y = {0.0, 0.0};  // sum conj(v_e) t_e at coordinate c
 #pragma unroll
-          for (int e = 0; e < kSubgroup; ++e) cfma_conj(y, vs[wave][e][c], ts[wave][e]);
-          const cx<T> u = us[wave][c];
+          for (int e = 0; e < kSubgroup; ++e) cfma_conj(y, widen(vs[wave][e][c]), widen(ts[wave][e]));
+          const cx<double> u = widen(us[wave][c]);
           if (BYROW) {
             a = im ? u.y : u.x;
             bv = im ? y.y : y.x;
@@ -345,9 +359,9 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
 #pragma unroll
       for (int q = 0; q < TPW; ++q)
         if (tx[q] >= 0) {
-          const T xa = As[g * LDW + tx[q] * 16 + c16];
-          const T yb = Bs[g * LDW + ty[q] * 16 + c16];
-          acc[q] = Mfma<T>::step(xa, yb, acc[q]);
+          const double xa = As[g * LDW + tx[q] * 16 + c16];
+          const double yb = Bs[g * LDW + ty[q] * 16 + c16];
+          acc[q] = Mfma<double>::step(xa, yb, acc[q]);
         }
     }
     // the next batch writes us/vs/ts first; its rows only after the barrier
@@ -360,9 +374,9 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
     if (tx[q] >= 0)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = tx[q] * 16 + Mfma<T>::out_row(lane, v);
+        const int row = tx[q] * 16 + Mfma<double>::out_row(lane, v);
         const int cl = ty[q] * 16 + (lane & 15);
-        S[row * WP + cl] = (double)acc[q][v];
+        S[row * WP + cl] = acc[q][v];
       }
   // S passes between threads through device memory: device-scope fences
   // around the barrier complete the stores and drop stale L1 lines
@@ -419,40 +433,79 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
     if (ok) break;
     __syncthreads();  // every thread is done with the failed attempt's column buffers
   }
+  // every thread finished reading S before the factorization's first
+  // barrier: the factor's rows (packed, L_ij at i (i + 1) / 2 + j), w (from
+  // the border row, conj(w)) and the status go over it
+  double2* F = (double2*)S;
+  double2* Wv = F + D * (D + 1) / 2;
   if (!ok) {
-    if (tid == 0) atomicAdd(A.flags, 1);
+    if (tid == 0) {
+      atomicAdd(A.flags, 1);
+      Wv[D] = make_double2(0.0, 0.0);
+    }
     return;
   }
-  if (tid == 0 && attempt > 0) atomicAdd(A.flags + 1, 1);
-  // the factor's rows over S (every thread finished reading S before the
-  // factorization's first barrier), packed: L_ij at i (i + 1) / 2 + j; the
-  // border row (conj(w), w = L^-1 (h + lam s_old)) to LDS as w
-  double2* F = (double2*)S;
+  if (tid == 0) {
+    if (attempt > 0) atomicAdd(A.flags + 1, 1);
+    Wv[D] = make_double2(1.0, 0.0);
+  }
 #pragma unroll
   for (int ia = 0; ia < NS; ++ia)
 #pragma unroll
     for (int jc = 0; jc <= ia; ++jc) {
       const int i = ga + GG * ia, j = gc + GG * jc;
       if (i < D && j <= i) F[i * (i + 1) / 2 + j] = make_double2(mr[ia][jc], mi[ia][jc]);
-      if (i == D && j < D) ys[j] = make_double2(mr[ia][jc], -mi[ia][jc]);
+      if (i == D && j < D) Wv[j] = make_double2(mr[ia][jc], -mi[ia][jc]);
     }
-  __threadfence();  // the factor overwrote S, which L1 may still hold
-  __syncthreads();
-  __threadfence();
-  if (wave != 0) return;  // one wavefront solves L^H s = w; no barrier follows
-  constexpr int TB = 4;   // unknowns per step
-#pragma unroll 1
-  for (int k0 = ((D - 1) / TB) * TB; k0 >= 0; k0 -= TB) {
+}
+
+// Back substitution L^H s = w of every factored slice, one wavefront per
+// slice (a launch after the fused kernel, so that many slices overlap the
+// latency of their factor rows).  Rows k0 .. k0+3 per step: every lane
+// solves the 4 x 4 diagonal block itself and updates its entries j < k0;
+// the next step's rows are loaded while the current one is used.
+template <typename T, int R>
+__global__ __launch_bounds__(64) void wide_backsub_kernel(WideArgs<T> A) {
+  typedef WideGeom<R> G;
+  constexpr int D = G::D, TB = 4, JP = (D + 63) / 64;
+  __shared__ double2 ys[D];
+  const int lane = threadIdx.x;
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int it0 = A.tile_items[tile], it1 = A.tile_items[tile + 1];
+  if (it0 == it1) return;
+  const double2* F = (const double2*)(A.region + (size_t)it0 * G::REGION);
+  const double2* Wv = F + D * (D + 1) / 2;
+  if (!(Wv[D].x > 0.0)) return;  // not factored: the slice keeps its values
+  for (int j = lane; j < D; j += 64) ys[j] = Wv[j];
+  wave_sync();
+  // the factor values one step uses: the diagonal block and rows k0+q at
+  // the lane's entries j = lane + 64 p < k0
+  double2 dd[TB][TB], lr[TB][JP];
+  auto fetch = [&](int k0, double2 (&d)[TB][TB], double2 (&l)[TB][JP]) {
     const int nb = D - k0 < TB ? D - k0 : TB;
-    double2 dd[TB][TB], yb[TB], sb[TB];
 #pragma unroll
     for (int q = 0; q < TB; ++q) {
-      const int r0 = (k0 + q) * (k0 + q + 1) / 2 + k0;
+      const int r0 = (k0 + q) * (k0 + q + 1) / 2;
 #pragma unroll
-      for (int t = 0; t <= q; ++t)
-        dd[q][t] = q < nb ? F[r0 + t] : make_double2(t == q ? 1.0 : 0.0, 0.0);
-      yb[q] = q < nb ? ys[k0 + q] : make_double2(0.0, 0.0);
+      for (int t = 0; t < TB; ++t)
+        d[q][t] = (q < nb && t <= q) ? F[r0 + k0 + t] : make_double2(t == q ? 1.0 : 0.0, 0.0);
+#pragma unroll
+      for (int p = 0; p < JP; ++p) {
+        const int j = lane + 64 * p;
+        l[q][p] = (q < nb && j < k0) ? F[r0 + j] : make_double2(0.0, 0.0);
+      }
     }
+  };
+  int k0 = ((D - 1) / TB) * TB;
+  fetch(k0, dd, lr);
+#pragma unroll 1
+  for (; k0 >= 0; k0 -= TB) {
+    double2 dn[TB][TB], ln[TB][JP];
+    if (k0 >= TB) fetch(k0 - TB, dn, ln);
+    const int nb = D - k0 < TB ? D - k0 : TB;
+    double2 yb[TB], sb[TB];
+#pragma unroll
+    for (int q = 0; q < TB; ++q) yb[q] = q < nb ? ys[k0 + q] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int q = TB - 1; q >= 0; --q) {  // s_q = (y_q - sum_{t>q} conj(L_tq) s_t) / L_qq
       double2 v = yb[q];
@@ -465,23 +518,34 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
       sb[q] = make_double2(v.x * rr, v.y * rr);
     }
     wave_sync();  // every lane has read the block's y
-    for (int j = lane; j < k0; j += 64) {  // y_j -= sum_q conj(L_(k0+q) j) s_q
-      double2 y = ys[j];
 #pragma unroll
-      for (int q = 0; q < TB; ++q) {
-        if (q < nb) {
-          const double2 l = F[(k0 + q) * (k0 + q + 1) / 2 + j];
-          y.x -= l.x * sb[q].x + l.y * sb[q].y;
-          y.y -= l.x * sb[q].y - l.y * sb[q].x;
+    for (int p = 0; p < JP; ++p) {  // y_j -= sum_q conj(L_(k0+q) j) s_q
+      const int j = lane + 64 * p;
+      if (j < k0) {
+        double2 y = ys[j];
+#pragma unroll
+        for (int q = 0; q < TB; ++q) {
+          y.x -= lr[q][p].x * sb[q].x + lr[q][p].y * sb[q].y;
+          y.y -= lr[q][p].x * sb[q].y - lr[q][p].y * sb[q].x;
         }
+        ys[j] = y;
       }
-      ys[j] = y;
     }
 #pragma unroll
     for (int q = 0; q < TB; ++q)
       if (lane == q && q < nb) ys[k0 + q] = sb[q];
     wave_sync();
+    if (k0 >= TB) {
+#pragma unroll
+      for (int q = 0; q < TB; ++q) {
+#pragma unroll
+        for (int t = 0; t < TB; ++t) dd[q][t] = dn[q][t];
+#pragma unroll
+        for (int p = 0; p < JP; ++p) lr[q][p] = ln[q][p];
+      }
+    }
   }
+  cx<T>* slice = A.slices + (int64_t)tile * D;
   for (int j = lane; j < D; j += 64) slice[j] = cx<T>{T(ys[j].x), T(ys[j].y)};
 }
 
@@ -501,6 +565,8 @@ bfc_status launch_inner_wide(const WideArgs<T>& a, int nslices, int by_row, hipS
       inner_wide_kernel<T, R, 1><<<nslices, kWideThreads, 0, st>>>(a);
     else
       inner_wide_kernel<T, R, 0><<<nslices, kWideThreads, 0, st>>>(a);
+    BFC_HIP_TRY(hipGetLastError());
+    wide_backsub_kernel<T, R><<<nslices, 64, 0, st>>>(a);
   }
   BFC_HIP_TRY(hipGetLastError());
   return BFC_OK;
