@@ -18,9 +18,12 @@ Besides the JSON fields of the bench contract the line carries:
   batching      the 64-instance workload swept in shared launches
   adam          ADAM butterfly completion (Sec. 5.1.2) from the same start
   adf           ADF butterfly completion (Sec. 5.1.3) from the same start
-  radon         the Radon-transform operator (Sec. 6.3) through the same sweep
-  green_c4      the paper's c = 4 Green's-function grid example (n = 16384,
-                L = 12) at rank 8
+  radon         the Radon-transform operator (Sec. 6.3) at the paper's
+                ranks: n = 4096 at r = 12 (radon) and n = 1024 at r = 10
+                (radon_1024)
+  green_c4      the paper's c = 4 Green's-function grids (Sec. 6.1) at
+                r = 11: n = 16384, L = 12 (green_c4) and n = 4096, L = 10
+                (green_c4_4096)
   scale         the 262144-point 2D-surface workload in the BF16-Gram mode
   learned_warm_start  the network that proposes starting cores, trained on
                 the method's own completions, against the Sec. 5.2 guess
@@ -978,57 +981,47 @@ def main():
         out["learned_warm_start"] = learned_record(args.learned_train, args.learned_epochs,
                                                    args.learned_eval)
 
-    def radon_record(sweeps=20):
-        """The Radon-transform operator of Sec. 6.3 on the 1024-point
-        instance (c = 4, r = 8, 30 n log2 n entries) through the same sweep in
-        this precision: throughput of steps timed as the headline (sweep plus
-        train residual) and the test error
-        after each of `sweeps` sweeps from the random start."""
-        wr = make_workload("radon-1024")
-        pr = bfc.init_cores(bfc.Config(n=wr.n, L=wr.L, r=wr.r, precision=args.precision),
-                            wr.rows, wr.cols, wr.vals, wr.cores0, device=dev)
-        secs, _, _, _ = timed_sweeps(bfc, torch, pr, 10, 2, False)
-        pr.close()
-        pr = bfc.init_cores(bfc.Config(n=wr.n, L=wr.L, r=wr.r, precision=args.precision),
-                            wr.rows, wr.cols, wr.vals, wr.cores0, device=dev)
-        te = []
-        for _ in range(sweeps):
-            bfc.sweep(pr)
-            te.append(bfc.relative_error(pr, wr.test_rows, wr.test_cols, wr.test_vals))
-        pr.close()
-        return {"workload": wr.name, "n": wr.n, "L": wr.L, "r": wr.r, "nnz": wr.nnz,
-                "entries_per_s": round(wr.nnz * 10 / secs, 1),
-                "ms_per_sweep": round(1e3 * secs / 10, 4),
-                "test_err_at_1": te[0], f"test_err_at_{sweeps}": te[-1]}
+    def paper_rank_record(name, precisions, sweeps=20):
+        """One of the paper's c = 4 examples at the rank the paper runs it
+        (Sec. 6.1, 6.3; ranks 10 - 12 take the fused wide-rank kernels):
+        per precision, the throughput of steps timed as the headline (sweep
+        plus train residual) and the test error after each of `sweeps`
+        (the paper's t_max) sweeps from the random start."""
+        w = make_workload(name)
+        rec = {"workload": w.name, "n": w.n, "L": w.L, "c": w.n >> w.L, "r": w.r,
+               "nnz": w.nnz, "ntest": w.ntest, "start": "random"}
+        for prec in precisions:
+            p = bfc.init_cores(bfc.Config(n=w.n, L=w.L, r=w.r, precision=prec), w.rows, w.cols,
+                               w.vals, w.cores0, device=dev)
+            secs, _, _, _ = timed_sweeps(bfc, torch, p, 5, 1, False)
+            p.close()
+            p = bfc.init_cores(bfc.Config(n=w.n, L=w.L, r=w.r, precision=prec), w.rows, w.cols,
+                               w.vals, w.cores0, device=dev)
+            te, tr = [], []
+            for _ in range(sweeps):
+                bfc.sweep(p)
+                te.append(bfc.relative_error(p, w.test_rows, w.test_cols, w.test_vals))
+                tr.append(bfc.train_error(p))
+            p.close()
+            hit = next((k + 1 for k, e in enumerate(te) if e <= 1e-3), None)
+            rec[prec] = {"entries_per_s": round(w.nnz * 5 / secs, 1),
+                         "ms_per_sweep": round(1e3 * secs / 5, 4),
+                         "test_err_at_1": te[0], "test_err_at_10": te[min(9, sweeps - 1)],
+                         f"test_err_at_{sweeps}": te[-1], f"train_err_at_{sweeps}": tr[-1],
+                         "sweeps_to_test_1e-3": hit}
+        return rec
 
     if not args.no_radon:
-        out["radon"] = radon_record()
-
-    def green_c4_record(sweeps=20):
-        """The paper's n = 16384 Green's-function grid example (c = 4,
-        L = 12, w = sqrt(n) pi / 5, 6 r n log2 n entries) at rank 8 in this
-        precision: throughput of steps timed as the headline and the test
-        error after each of `sweeps` (the paper's t_max) sweeps from the
-        random start."""
-        wg = make_workload("green-planes-16384-c4")
-        pg = bfc.init_cores(bfc.Config(n=wg.n, L=wg.L, r=wg.r, precision=args.precision),
-                            wg.rows, wg.cols, wg.vals, wg.cores0, device=dev)
-        secs, _, _, _ = timed_sweeps(bfc, torch, pg, 10, 2, False)
-        pg.close()
-        pg = bfc.init_cores(bfc.Config(n=wg.n, L=wg.L, r=wg.r, precision=args.precision),
-                            wg.rows, wg.cols, wg.vals, wg.cores0, device=dev)
-        te = []
-        for _ in range(sweeps):
-            bfc.sweep(pg)
-            te.append(bfc.relative_error(pg, wg.test_rows, wg.test_cols, wg.test_vals))
-        pg.close()
-        return {"workload": wg.name, "n": wg.n, "L": wg.L, "c": wg.c, "r": wg.r, "nnz": wg.nnz,
-                "entries_per_s": round(wg.nnz * 10 / secs, 1),
-                "ms_per_sweep": round(1e3 * secs / 10, 4),
-                "test_err_at_1": te[0], f"test_err_at_{sweeps}": te[-1]}
+        # Sec. 6.3: n = 4096 at r = 12 (the printed training / test counts)
+        # and n = 1024 at r = 10 (30 n log2 n entries)
+        out["radon"] = paper_rank_record("radon-4096-r12", ("c64", "c128"))
+        out["radon_1024"] = paper_rank_record("radon-1024-r10", ("c64",))
 
     if not args.no_green_c4:
-        out["green_c4"] = green_c4_record()
+        # Sec. 6.1: the c = 4 grids at r = 11, n = 16384 (6 r n log2 n
+        # entries) and n = 4096 (66 n log2 n entries)
+        out["green_c4"] = paper_rank_record("green-planes-16384-c4-r11", ("c64", "c128"))
+        out["green_c4_4096"] = paper_rank_record("green-planes-4096-c4-r11", ("c64",))
 
     def scale_record(sweeps=20):
         """The 2D-surface scale workload (n = 262144, L = 12, r = 8, two

@@ -284,6 +284,9 @@ static bfc_status sweep_via_graph(bfc_problem* p, hipStream_t st) {
       return s;
     }
     BFC_HIP_TRY(e);
+    // whether the captured last core update leaves the per-fiber residual
+    // norms (the narrow ranks' outer kernel does, the wide ranks' does not)
+    p->graph_fused_res = p->fused_res_valid;
     p->sweep_graph = g;
     BFC_HIP_TRY(hipGraphInstantiate(&p->sweep_exec, g, nullptr, nullptr, 0));
   }
@@ -291,7 +294,7 @@ static bfc_status sweep_via_graph(bfc_problem* p, hipStream_t st) {
   // the state a sweep leaves (host-side bookkeeping the replay does not run)
   for (auto& E : p->rlev) E.valid = false;
   for (size_t q = 2; q < p->llev.size(); ++q) p->llev[q].valid = true;
-  p->fused_res_valid = true;
+  p->fused_res_valid = p->graph_fused_res;
   return BFC_OK;
 }
 

@@ -179,6 +179,7 @@ struct Problem {
   int32_t* bad_flag = nullptr;       // non-finite value seen by bfc_set_values
   double* fused_res = nullptr;       // 2 per fiber of the last core: residual norms
   bool fused_res_valid = false;      // fused_res belongs to the current cores
+  bool graph_fused_res = false;      // a replay of sweep_graph leaves fused_res valid
   size_t red_len = 0;
   double* red_host = nullptr;        // pinned, 2 doubles
   std::vector<void*> allocs;         // everything hipMalloc'd

@@ -142,21 +142,31 @@ def test_wide_predict_and_residual_r12():
 
 
 def test_wide_sweeps_descend_with_graphs():
-    # graph-captured sweeps at r = 10 equal the uncaptured ones and descend
+    # graph-captured sweeps (a non-default stream) at r = 10 equal the
+    # uncaptured ones, descend, and leave a training error equal to the one
+    # recomputed over the entries (the wide outer kernel leaves no fused
+    # residual norms, so the replay must not mark them valid)
+    import torch
+
     n, L, r = 1024, 8, 10
     rows, cols, vals, _, _, _, cores0 = _instance(n, L, r, 30 * n * 10, 11)
+    st = torch.cuda.Stream()
     outs, errs = [], []
-    for graphs in (True, False):
-        prob = bfc.init_cores(bfc.Config(n=n, L=L, r=r, precision="c64"), rows, cols, vals,
-                              cores0, device=DEV)
-        bfc.use_graphs(prob, graphs)
-        e = []
-        for _ in range(4):
-            bfc.sweep(prob)
-            e.append(bfc.relative_error(prob, rows, cols, vals))
-        outs.append(bfc.get_cores(prob).cpu().numpy())
-        errs.append(e)
-        prob.close()
+    with torch.cuda.stream(st):
+        for graphs in (True, False):
+            prob = bfc.init_cores(bfc.Config(n=n, L=L, r=r, precision="c64"), rows, cols, vals,
+                                  cores0, device=DEV)
+            bfc.use_graphs(prob, graphs)
+            e = []
+            for _ in range(4):
+                bfc.sweep(prob)
+                tr = bfc.train_error(prob)
+                ref = bfc.relative_error(prob, rows, cols, vals)
+                assert tr == pytest.approx(ref, rel=1e-4), (graphs, tr, ref)
+                e.append(ref)
+            outs.append(bfc.get_cores(prob).cpu().numpy())
+            errs.append(e)
+            prob.close()
     assert np.array_equal(outs[0], outs[1])
     assert all(b <= a * (1 + 1e-6) for a, b in zip(errs[0], errs[0][1:])), errs[0]
 
