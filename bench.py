@@ -990,10 +990,25 @@ def main():
         w = make_workload(name)
         rec = {"workload": w.name, "n": w.n, "L": w.L, "c": w.n >> w.L, "r": w.r,
                "nnz": w.nnz, "ntest": w.ntest, "start": "random"}
+        d = w.r * w.r
         for prec in precisions:
             p = bfc.init_cores(bfc.Config(n=w.n, L=w.L, r=w.r, precision=prec), w.rows, w.cols,
                                w.vals, w.cores0, device=dev)
             secs, _, _, _ = timed_sweeps(bfc, torch, p, 5, 1, False)
+            # the inner core update (one kind: the fused Gram + factorization
+            # launch and its back substitution at r > 8) against the FP64
+            # matrix roof, from the grouped-Gram flops of the SURVEY model
+            # plus the slices' Cholesky and triangular solves
+            _, _, kern, _ = timed_sweeps(bfc, torch, p, 2, 0, True)
+            st = [bfc.core_stats(p, q) for q in range(1, w.L + 1)]
+            flops = sum(inner_gram_flops(x, w.nnz, w.r) + x["blocks"] * (4 * d ** 3 // 3 + 16 * d * d)
+                        for x in st) / w.L
+            ms, nl = kern["inner_gram"]
+            t_launch = ms * 1e-3 / max(nl, 1)
+            inner = {"avg_launch_us": round(1e6 * t_launch, 2), "flops_per_launch": round(flops),
+                     "achieved_TFs": round(flops / t_launch / 1e12, 3),
+                     "peak_TFs": PEAKS["fp64_matrix_TFs"],
+                     "frac": round(flops / t_launch / 1e12 / PEAKS["fp64_matrix_TFs"], 4)}
             p.close()
             p = bfc.init_cores(bfc.Config(n=w.n, L=w.L, r=w.r, precision=prec), w.rows, w.cols,
                                w.vals, w.cores0, device=dev)
@@ -1008,7 +1023,7 @@ def main():
                          "ms_per_sweep": round(1e3 * secs / 5, 4),
                          "test_err_at_1": te[0], "test_err_at_10": te[min(9, sweeps - 1)],
                          f"test_err_at_{sweeps}": te[-1], f"train_err_at_{sweeps}": tr[-1],
-                         "sweeps_to_test_1e-3": hit}
+                         "sweeps_to_test_1e-3": hit, "inner_update": inner}
         return rec
 
     if not args.no_radon:
