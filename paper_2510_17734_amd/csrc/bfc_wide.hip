@@ -378,11 +378,10 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
         const int cl = ty[q] * 16 + (lane & 15);
         S[row * WP + cl] = acc[q][v];
       }
-  // S passes between threads through device memory: device-scope fences
-  // around the barrier complete the stores and drop stale L1 lines
-  __threadfence();
+  // S passes between the workgroup's threads through device memory; the
+  // workgroup barrier orders it (one CU, one L1 and L2: no device-scope
+  // fence, which on this chip writes back and invalidates the XCD's L2)
   __syncthreads();
-  __threadfence();
   cx<T>* slice = A.slices + (int64_t)tile * D;
   for (int i = tid; i < D; i += NT) {
     dg[i] = inner_K<R>(S, WP, i, i).x;
