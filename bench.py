@@ -44,6 +44,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# ranks above this run the fused per-slice kernels, which form every Gram in
+# FP64 (both precisions) and factor in the same launch
+WIDE_RANK = 8
+
 PEAKS = {  # MI355X published dense peaks
     "hbm_GBs": 8000.0,
     "fp32_TFs": 157.3,
@@ -98,6 +102,9 @@ def sweep_model(stats, w, cbytes, env_total):
     m["inner_solve"] = (0, sum(stats[p]["blocks"] * (4 * d ** 3 // 3 + 16 * d * d)
                                for p in range(1, L + 1)))
     m["outer"] = (2 * nnz * eb, 2 * outer_flops(nnz, r))
+    if r > WIDE_RANK:  # one fused launch per inner core: Gram and factorization
+        m["inner_gram"] = (m["inner_gram"][0], m["inner_gram"][1] + m["inner_solve"][1])
+        m["inner_solve"] = (0, 0)
     m["env"] = (0, env_flops(env_total, r))
     m["residual"] = (0, nnz * 8 * r)
     return m
@@ -207,22 +214,32 @@ def cpu_baseline(w, budget_s=25.0):
     """The oracle, untuned, on a bounded sample: two core updates (the first
     outer core and the middle inner core) of the same workload; the sweep
     time is estimated as 2 t(outer) + L t(inner)."""
+    import contextlib
+
     import numpy as np  # noqa: F401
+    import scipy.linalg  # noqa: F401
     import oracle
 
+    # numpy and scipy each bring an OpenBLAS pool; both at full width spin
+    # against each other (the oracle's small factorizations then run some
+    # twenty times slower), so each pool gets half of the CPU share (at most
+    # 16 CPUs per GPU on the box)
+    share = min(len(os.sched_getaffinity(0)), 16)
+    threads = max(1, share // 2)
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_limits
 
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        limit = threadpool_limits(limits=threads)
     except Exception:
-        threads = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    oracle.update_core(w.cores0, 0, w.rows, w.cols, w.vals, w.L)
-    t_outer = time.perf_counter() - t0
-    pm = max(1, w.L // 2)
-    t0 = time.perf_counter()
-    oracle.update_core(w.cores0, pm, w.rows, w.cols, w.vals, w.L)
-    t_inner = time.perf_counter() - t0
+        limit = contextlib.nullcontext()
+    with limit:
+        t0 = time.perf_counter()
+        oracle.update_core(w.cores0, 0, w.rows, w.cols, w.vals, w.L)
+        t_outer = time.perf_counter() - t0
+        pm = max(1, w.L // 2)
+        t0 = time.perf_counter()
+        oracle.update_core(w.cores0, pm, w.rows, w.cols, w.vals, w.L)
+        t_inner = time.perf_counter() - t0
     sweep_s = 2 * t_outer + w.L * t_inner
     model = "unknown"
     try:
@@ -237,6 +254,7 @@ def cpu_baseline(w, budget_s=25.0):
         "value": w.nnz / sweep_s,
         "unit": "observed entries/s per ALS sweep",
         "cores": threads,
+        "blas_pools": 2,
         "nproc": len(os.sched_getaffinity(0)),
         "cpu_model": model,
         "kind": "oracle",
@@ -246,7 +264,11 @@ def cpu_baseline(w, budget_s=25.0):
 
 
 KIND_PATTERNS = (("inner_gram", "inner_gram_kernel"), ("inner_solve", "inner_solve_kernel"),
-                 ("outer", "outer_update_kernel"), ("env", "_level_kernel"),
+                 # ranks above 8: the fused Gram + factorization launch and its
+                 # back substitution form one inner core update
+                 ("inner_gram", "inner_wide_kernel"), ("inner_gram", "wide_backsub_kernel"),
+                 ("outer", "outer_update_kernel"), ("outer", "outer_wide_kernel"),
+                 ("env", "_level_kernel"),
                  ("env", "env_right_direct_kernel"),
                  ("residual", "residual_observed_kernel"))
 
@@ -623,7 +645,7 @@ def main():
     dbytes = models[dom][0] / per_launch
     dflops = models[dom][1] / per_launch
     mat_peak = {"c64": PEAKS["fp32_matrix_TFs"], "c128": PEAKS["fp64_matrix_TFs"]}[args.precision]
-    if dom == "inner_solve":
+    if dom == "inner_solve" or w.r > WIDE_RANK:
         mat_peak = PEAKS["fp64_matrix_TFs"]
     t_hbm = dbytes / (PEAKS["hbm_GBs"] * 1e9)
     t_cmp = dflops / (mat_peak * 1e12)
