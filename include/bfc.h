@@ -255,6 +255,26 @@ bfc_status bfc_set_values(bfc_problem* p, const void* d_vals, void* hip_stream);
 bfc_status bfc_loss_gradient(bfc_problem* p, float scale, void* d_grad, int32_t grad_fp64,
                              double* loss, void* hip_stream);
 
+/*
+ * The loss gradients of `count` matrices observed on this problem's positions
+ * (the instances of a training batch), one after another on hip_stream with
+ * one synchronization at the end: for b = 0 .. count-1 the problem takes the
+ * values d_vals[b] (as bfc_set_values) and the cores d_cores[b] (as
+ * bfc_set_cores_f32), then scales[b] * g is written to d_grads[b] (as
+ * bfc_loss_gradient, FP32 or FP64 by grad_fp64) and losses[b] =
+ * scales[b] * phi.  d_vals, d_cores and d_grads are host arrays of count
+ * device pointers (caller owned, each d_grads[b] distinct), scales and
+ * losses host arrays of count values.  The problem keeps the last instance's
+ * values and cores.  Results equal count calls of the three single-instance
+ * functions bit for bit.  BFC_EINVAL for count < 1 or a NULL pointer,
+ * BFC_ENONFINITE if any instance's values hold a NaN or Inf (every gradient
+ * is still written; none of them should be used).
+ */
+bfc_status bfc_loss_gradient_batch(bfc_problem* p, int32_t count, const void* const* d_vals,
+                                   const float* const* d_cores, const float* scales,
+                                   void* const* d_grads, int32_t grad_fp64, double* losses,
+                                   void* hip_stream);
+
 /* Synchronize hip_stream and report (and clear) pending solve failures. */
 bfc_status bfc_sync_status(bfc_problem* p, void* hip_stream);
 

@@ -66,6 +66,7 @@ EXPORTS = (
     "bfc_set_cores_f32",
     "bfc_set_values",
     "bfc_loss_gradient",
+    "bfc_loss_gradient_batch",
     "bfc_mlp_forward",
     "bfc_mlp_backward",
     "bfc_mlp_forward_bf16",
@@ -179,6 +180,10 @@ def load(path: str | None = None) -> ctypes.CDLL:
     f = ctypes.c_float
     lib.bfc_loss_gradient.argtypes = [P, f, vp, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.bfc_loss_gradient.restype = i32
+    lib.bfc_loss_gradient_batch.argtypes = [P, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                            ctypes.POINTER(f), ctypes.POINTER(vp), i32,
+                                            ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfc_loss_gradient_batch.restype = i32
     lib.bfc_mlp_forward.argtypes = [i64, i64, i64, vp, vp, vp, i32, vp, vp]
     lib.bfc_mlp_forward.restype = i32
     lib.bfc_mlp_backward.argtypes = [i64, i64, i64, vp, vp, vp, vp, i32, vp, vp, vp, vp]

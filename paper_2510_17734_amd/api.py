@@ -464,6 +464,41 @@ def loss_gradient(p: Problem, out: torch.Tensor | None = None, scale: float = 1.
     return out, loss.value
 
 
+def loss_gradient_batch(p: Problem, vals, cores, scales, out=None, fp64: bool = False,
+                        stream=None):
+    """bfc_loss_gradient_batch: the loss gradients of several matrices on this
+    problem's positions with one synchronization.  vals: device complex128
+    tensors (nnz each), cores: device float32 tensors (bfc_set_cores_f32
+    layout), scales: floats; out: device tensors for the gradients (created
+    when None).  Returns (gradients, losses)."""
+    count = len(vals)
+    if len(cores) != count or len(scales) != count or count < 1:
+        raise ValueError("loss_gradient_batch needs equally many values, cores and scales")
+    m = num_params(p.cfg.n, p.cfg.L, p.cfg.r)
+    dt = torch.float64 if fp64 else torch.float32
+    if out is None:
+        out = [torch.empty(2 * m, dtype=dt, device=p.device) for _ in range(count)]
+    for t in out:
+        if t.dtype != dt or t.numel() != 2 * m or not t.is_contiguous():
+            raise ValueError("loss_gradient_batch output has the wrong type or size")
+    for v in vals:
+        if v.dtype != torch.complex128 or v.numel() != p.nnz or not v.is_contiguous():
+            raise ValueError("loss_gradient_batch values must be nnz contiguous complex128")
+    for c in cores:
+        if c.dtype != torch.float32 or c.numel() != 2 * m or not c.is_contiguous():
+            raise ValueError("loss_gradient_batch cores must be contiguous float32")
+    vp = ctypes.c_void_p
+    pv = (vp * count)(*[v.data_ptr() for v in vals])
+    pc = (vp * count)(*[c.data_ptr() for c in cores])
+    pg = (vp * count)(*[g.data_ptr() for g in out])
+    sc = (ctypes.c_float * count)(*[float(x) for x in scales])
+    losses = (ctypes.c_double * count)()
+    _check(_lib.load().bfc_loss_gradient_batch(p.handle, count, pv, pc, sc, pg,
+                                               1 if fp64 else 0, losses, _stream(stream)),
+           "bfc_loss_gradient_batch")
+    return out, [float(x) for x in losses]
+
+
 def _f32(t: torch.Tensor, name: str):
     if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
         raise ValueError(f"{name} must be a contiguous float32 device tensor")

@@ -562,6 +562,65 @@ bfc_status bfc_loss_gradient(bfc_problem* p, float scale, void* d_grad, int32_t 
   return BFC_OK;
 }
 
+bfc_status bfc_loss_gradient_batch(bfc_problem* p, int32_t count, const void* const* d_vals,
+                                   const float* const* d_cores, const float* scales,
+                                   void* const* d_grads, int32_t grad_fp64, double* losses,
+                                   void* hip_stream) {
+  if (!p || count < 1 || !d_vals || !d_cores || !scales || !d_grads || !losses) {
+    set_error("bad loss_gradient_batch arguments");
+    return BFC_EINVAL;
+  }
+  for (int32_t b = 0; b < count; ++b)
+    if (!d_vals[b] || !d_cores[b] || !d_grads[b] || !(scales[b] == scales[b])) {
+      set_error("bfc_loss_gradient_batch: a NULL pointer or NaN scale at instance " +
+                std::to_string(b));
+      return BFC_EINVAL;
+    }
+  if (p->r > BFC_MAX_RANK_FULL) {
+    set_error("bfc_loss_gradient_batch: supports r <= 8");
+    return BFC_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t real = p->elem / 2;
+  if (p->L >= 1 && p->adam_part_items < p->max_items) {
+    if (p->adam_part) BFC_TRY(dev_free(p, p->adam_part));
+    p->adam_part = nullptr;
+    BFC_TRY(dev_alloc(p, &p->adam_part,
+                      (size_t)std::max(p->max_items, 1) * 2 * p->r * p->r * real));
+    p->adam_part_items = std::max(p->max_items, 1);
+  }
+  if (!p->grad) BFC_TRY(dev_alloc(p, &p->grad, (size_t)p->nparams * p->elem));
+  if (!p->bad_flag) BFC_TRY(dev_alloc(p, (void**)&p->bad_flag, 4));
+  if (p->batch_res_cap < count) {
+    void* fresh = nullptr;
+    BFC_TRY(dev_alloc(p, &fresh, (size_t)count * 2 * sizeof(double)));
+    if (p->batch_res) BFC_TRY(dev_free(p, p->batch_res));
+    p->batch_res = (double*)fresh;
+    p->batch_res_cap = count;
+  }
+  // the same launches as count calls of bfc_set_values, bfc_set_cores_f32
+  // and bfc_loss_gradient, without their synchronizations
+  BFC_HIP_TRY(hipMemsetAsync(p->bad_flag, 0, 4, st));
+  for (int32_t b = 0; b < count; ++b) {
+    BFC_TRY(enqueue_set_values(p, d_vals[b], st));
+    BFC_TRY(launch_cores_from_f32(p, d_cores[b], st));
+    BFC_TRY(launch_loss_gradient(p, scales[b], d_grads[b], grad_fp64 != 0, st));
+    BFC_TRY(launch_residual_observed(p, p->batch_res + 2 * b, st));
+  }
+  std::vector<double> res((size_t)count * 2);
+  int32_t bad = 0;
+  BFC_HIP_TRY(hipMemcpyAsync(res.data(), p->batch_res, res.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipMemcpyAsync(&bad, p->bad_flag, 4, hipMemcpyDeviceToHost, st));
+  BFC_HIP_TRY(hipStreamSynchronize(st));
+  for (int32_t b = 0; b < count; ++b) losses[b] = 0.5 * (double)scales[b] * res[2 * b];
+  if (bad) {
+    set_error("bfc_loss_gradient_batch: an instance's values hold a NaN or Inf");
+    return BFC_ENONFINITE;
+  }
+  return BFC_OK;
+}
+
 bfc_status bfc_sync_status(bfc_problem* p, void* hip_stream) {
   if (!p) {
     set_error("null problem");

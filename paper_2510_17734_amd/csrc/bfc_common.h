@@ -177,6 +177,8 @@ struct Problem {
   void* adf_dir = nullptr;           // ADF directions of an inner core's slices
   void* grad = nullptr;              // per-core gradients (bfc_loss_gradient)
   int32_t* bad_flag = nullptr;       // non-finite value seen by bfc_set_values
+  double* batch_res = nullptr;       // bfc_loss_gradient_batch: 2 residual norms per instance
+  int32_t batch_res_cap = 0;         // instances batch_res holds
   double* fused_res = nullptr;       // 2 per fiber of the last core: residual norms
   bool fused_res_valid = false;      // fused_res belongs to the current cores
   bool graph_fused_res = false;      // a replay of sweep_graph leaves fused_res valid
@@ -247,6 +249,7 @@ bfc_status launch_adam_core(Problem* P, int core, int t, double alpha, double be
                             double beta2, double sigma, hipStream_t st);
 bfc_status launch_adf_sweep(Problem* P, hipStream_t st);
 bfc_status launch_set_values(Problem* P, const void* d_vals, hipStream_t st);
+bfc_status enqueue_set_values(Problem* P, const void* d_vals, hipStream_t st);
 bfc_status launch_cores_from_f32(Problem* P, const float* src, hipStream_t st);
 bfc_status launch_loss_gradient(Problem* P, float scale, void* out, int out_fp64, hipStream_t st);
 bfc_status build_items(Problem* P, int core, hipStream_t st);

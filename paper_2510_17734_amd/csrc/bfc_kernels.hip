@@ -2756,10 +2756,11 @@ __global__ void values_to_layout_kernel(const int32_t* perm, const double2* src,
   dst[k] = cx<T>{T(v.x), T(v.y)};
 }
 
-bfc_status launch_set_values(Problem* P, const void* d_vals, hipStream_t st) {
+// Values into every core's sorted layout; non-finite values set *bad_flag
+// (which the caller clears beforehand).  Asynchronous.
+bfc_status enqueue_set_values(Problem* P, const void* d_vals, hipStream_t st) {
   const int64_t nnz = P->nnz;
   if (nnz == 0) return BFC_OK;
-  BFC_HIP_TRY(hipMemsetAsync(P->bad_flag, 0, 4, st));
   for (int p = 0; p <= P->L + 1; ++p) {
     const CoreLayout& C = P->lay[p];
     if (P->prec == BFC_C128)
@@ -2771,6 +2772,13 @@ bfc_status launch_set_values(Problem* P, const void* d_vals, hipStream_t st) {
     BFC_HIP_TRY(hipGetLastError());
   }
   P->fused_res_valid = false;
+  return BFC_OK;
+}
+
+bfc_status launch_set_values(Problem* P, const void* d_vals, hipStream_t st) {
+  if (P->nnz == 0) return BFC_OK;
+  BFC_HIP_TRY(hipMemsetAsync(P->bad_flag, 0, 4, st));
+  BFC_TRY(enqueue_set_values(P, d_vals, st));
   int32_t bad = 0;
   BFC_HIP_TRY(hipMemcpyAsync(&bad, P->bad_flag, 4, hipMemcpyDeviceToHost, st));
   BFC_HIP_TRY(hipStreamSynchronize(st));

@@ -178,11 +178,11 @@ def train(net: WarmStartNet, ds: Dataset, prob, *, epochs: int, batch: int = 32,
             acts = net.forward_train(X)
             out = acts[-1]
             d_out = torch.empty_like(out)
-            for bi, k in enumerate(idx):
-                bfc.set_values(prob, ds.targets[k])
-                bfc.set_cores_f32(prob, out[bi])
-                _, loss = bfc.loss_gradient(prob, out=d_out[bi], scale=ds.scales[k] / len(idx))
-                tot += loss
+            # the batch's loss gradients, one call and one synchronization
+            _, losses = bfc.loss_gradient_batch(
+                prob, [ds.targets[k] for k in idx], [out[bi] for bi in range(len(idx))],
+                [ds.scales[k] / len(idx) for k in idx], out=[d_out[bi] for bi in range(len(idx))])
+            tot += sum(losses)
             net.step(net.backward(acts, d_out), lr)
             nb += 1
         history.append(tot / nb)

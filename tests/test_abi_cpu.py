@@ -90,6 +90,26 @@ def test_null_problem_calls():
     lib.bfc_destroy(None)
 
 
+def test_loss_gradient_batch_argument_checks():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    one = (vp * 1)(vp(0x1000))
+    sc = (ctypes.c_float * 1)(1.0)
+    out = (ctypes.c_double * 1)()
+    # rejected before any device access: null problem, zero count, null arrays
+    assert lib.bfc_loss_gradient_batch(None, 1, one, one, sc, one, 0, out, None) == _lib.BFC_EINVAL
+    assert lib.bfc_loss_gradient_batch(vp(0x1000), 0, one, one, sc, one, 0, out, None) == \
+        _lib.BFC_EINVAL
+    assert lib.bfc_loss_gradient_batch(vp(0x1000), 1, None, one, sc, one, 0, out, None) == \
+        _lib.BFC_EINVAL
+    assert lib.bfc_loss_gradient_batch(vp(0x1000), 1, one, one, sc, one, 0, None, None) == \
+        _lib.BFC_EINVAL
+    nul = (vp * 1)(None)
+    assert lib.bfc_loss_gradient_batch(vp(0x1000), 1, one, nul, sc, one, 0, out, None) == \
+        _lib.BFC_EINVAL
+    assert "instance 0" in lib.bfc_last_error().decode()
+
+
 def test_batch_argument_checks():
     lib = _lib.load()
     h = ctypes.c_void_p(1)

@@ -173,6 +173,41 @@ def test_set_values_and_f32_cores():
     prob.close()
 
 
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_loss_gradient_batch_equals_single_calls(prec):
+    # four matrices on the same positions: the batched call gives the
+    # single-instance results bit for bit, and a NaN value is reported
+    n, L, r, nnz = 256, 4, 4, 8155
+    prob, rows, cols, vals, cores = _problem(n, L, r, nnz, 7, prec)
+    m = bfc.num_params(n, L, r)
+    rng = np.random.default_rng(9)
+    vs, cs, scales = [], [], []
+    for b in range(4):
+        v = green_line_entries(n, 2 * math.pi * (3 + b), rows, cols) * (1 + 0.25j * b)
+        vs.append(torch.as_tensor(v, dtype=torch.complex128, device=DEV))
+        c = bfc.flatten_cores(random_cores(n, L, r, 40 + b, scale=1.0))
+        cs.append(torch.view_as_real(torch.as_tensor(c)).reshape(-1).to(torch.float32).to(DEV))
+        scales.append(float(rng.uniform(0.5, 2.0)))
+    for fp64 in (False, True):
+        single, sl = [], []
+        for b in range(4):
+            bfc.set_values(prob, vs[b])
+            bfc.set_cores_f32(prob, cs[b])
+            g, loss = bfc.loss_gradient(prob, scale=scales[b], fp64=fp64)
+            single.append(g.clone())
+            sl.append(loss)
+        grads, losses = bfc.loss_gradient_batch(prob, vs, cs, scales, fp64=fp64)
+        for b in range(4):
+            assert torch.equal(grads[b], single[b]), (fp64, b)
+            assert losses[b] == sl[b], (fp64, b)
+        assert all(g.numel() == 2 * m for g in grads)
+    bad = vs[2].clone()
+    bad[5] = complex(float("nan"), 0.0)
+    with pytest.raises(bfc.BfcError):
+        bfc.loss_gradient_batch(prob, [vs[0], bad], cs[:2], scales[:2])
+    prob.close()
+
+
 def test_trained_network_beats_the_lowrank_guess_and_random_starts():
     """A short training run (128 completions, 10 epochs) already lowers the
     training loss and, on 12 held-out operators, needs fewer sweeps to test
