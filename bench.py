@@ -272,6 +272,9 @@ KIND_PATTERNS = (("inner_gram", "inner_gram_kernel"), ("inner_solve", "inner_sol
                  # ranks above 8: the fused Gram + factorization launch and its
                  # back substitution form one inner core update
                  ("inner_gram", "inner_wide_kernel"), ("inner_gram", "wide_backsub_kernel"),
+                 # BF16-Gram mode: the library times the refinement solve with
+                 # the slice solves and the entries' residual vectors on their own
+                 ("inner_solve", "inner_refine_kernel"), ("inner_ir", "inner_ir_kernel"),
                  ("outer", "outer_update_kernel"), ("outer", "outer_wide_kernel"),
                  ("env", "_level_kernel"),
                  ("env", "env_right_direct_kernel"),
