@@ -29,7 +29,13 @@
 extern "C" {
 #endif
 
-/* Y = act(X W + b); b may be NULL (no bias).  FP32 throughout. */
+/* Y = act(X W + b); b may be NULL (no bias).  FP32 throughout.
+ * Products with few 64 x 64 output tiles over a long reduction (k >= 2048)
+ * are split over k into partial tiles summed in a fixed order, in a
+ * workspace kept per GPU for the life of the process (first use allocates
+ * it); calls on one stream are ordered, calls that overlap on different
+ * streams of one GPU are not supported.  The same holds for the two
+ * products of bfc_mlp_backward. */
 bfc_status bfc_mlp_forward(int64_t m, int64_t k, int64_t n, const float* X, const float* W,
                            const float* b, int32_t act, float* Y, void* hip_stream);
 

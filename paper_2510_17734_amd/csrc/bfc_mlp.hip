@@ -9,7 +9,9 @@
 // never stored.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "bfc_common.h"
@@ -37,11 +39,13 @@ struct Operand {
 };
 
 // C[i][j] = act(sum_k A(i, k) B(j, k) + bias[j]); A is M x K, B is N x K as
-// (outer, k) operands.
+// (outer, k) operands.  Split over k (gridDim.z > 1): block z sums k in
+// [z kc, (z+1) kc) and stores its plain partial tile at C + z M N (ldc = N).
 template <typename TI>
-__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, Operand A,
-                                                   Operand B, const float* bias, int act,
-                                                   float* C, uint16_t* Ch, int64_t ldc) {
+__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kc,
+                                                   Operand A, Operand B, const float* bias,
+                                                   int act, float* C, uint16_t* Ch,
+                                                   int64_t ldc) {
   __shared__ float As[kSlab][kTile + kPad];
   __shared__ float Bs[kSlab][kTile + kPad];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -55,7 +59,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = 0; k0 < K; k0 += kSlab) {
+  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t ke = kb + kc < K ? kb + kc : K;
+  if (gridDim.z > 1) C += (int64_t)blockIdx.z * M * N;
+  for (int64_t k0 = kb; k0 < ke; k0 += kSlab) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
       const int kk = a_outer_fast ? (e >> 6) : (e & (kSlab - 1));
       const int64_t gi = i0 + o, gk = k0 + kk;
       float v = 0.f;
-      if (gi < M && gk < K) {
+      if (gi < M && gk < ke) {
         const int64_t idx = gi * A.s_outer + gk * A.s_k;
         v = load_as_float(ap, idx);
         if (A.mask && !(A.mask[idx] > 0.f)) v = 0.f;
@@ -78,7 +85,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
       const int kk = b_outer_fast ? (e >> 6) : (e & (kSlab - 1));
       const int64_t gj = j0 + o, gk = k0 + kk;
       float v = 0.f;
-      if (gj < N && gk < K) {
+      if (gj < N && gk < ke) {
         const int64_t idx = gj * B.s_outer + gk * B.s_k;
         v = load_as_float(bp, idx);
         if (B.mask && !(B.mask[idx] > 0.f)) v = 0.f;
@@ -196,6 +203,22 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int64_t M, int64_t N, in
       }
 }
 
+// The split products' partial tiles summed in chunk order, then bias and
+// activation, as the unsplit store does.
+__global__ void splitk_reduce_kernel(int64_t M, int64_t N, int S, const float* ws,
+                                     const float* bias, int act, float* C, uint16_t* Ch,
+                                     int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t i = e / N, j = e % N;
+  float o = 0.f;
+  for (int z = 0; z < S; ++z) o += ws[(int64_t)z * M * N + e];
+  o += bias ? bias[j] : 0.f;
+  if (act == 1) o = o > 0.f ? o : 0.f;
+  if (C) C[i * ldc + j] = o;
+  if (Ch) Ch[i * ldc + j] = to_bf16(o);
+}
+
 // db[j] = sum_i dY[i][j] (* (Y[i][j] > 0) for ReLU), rows summed in order
 __global__ void colsum_kernel(int64_t m, int64_t n, const float* dY, const float* Y, float* db) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -227,6 +250,39 @@ __global__ void to_bf16_kernel(int64_t count, const float* src, uint16_t* dst) {
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Workgroups a product should fill before its reduction is split, and the
+// shortest chunk of the reduction one split block takes.
+constexpr int64_t kSplitTarget = 1024, kMinChunk = 1024;
+
+// The split products' partial tiles: one workspace per GPU, grown on demand
+// and kept until the process ends.  Work on one stream is ordered; calls that
+// overlap on different streams of one GPU would share it.
+bfc_status splitk_workspace(size_t floats, float** out) {
+  static std::mutex mu;
+  static void* buf[64] = {};
+  static size_t cap[64] = {};
+  int dev = 0;
+  BFC_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_error("bfc_mlp: device index out of range");
+    return BFC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (cap[dev] < floats) {
+    void* fresh = nullptr;
+    BFC_HIP_TRY(lib_malloc(&fresh, floats * sizeof(float)));
+    if (buf[dev]) {
+      // work queued on the old buffer finishes before it goes
+      BFC_HIP_TRY(hipDeviceSynchronize());
+      (void)hipFree(buf[dev]);
+    }
+    buf[dev] = fresh;
+    cap[dev] = floats;
+  }
+  *out = (float*)buf[dev];
+  return BFC_OK;
+}
+
 template <typename TI>
 bfc_status gemm(int64_t M, int64_t N, int64_t K, Operand A, Operand B, const float* bias,
                 int act, float* C, uint16_t* Ch, int64_t ldc, hipStream_t st) {
@@ -236,8 +292,27 @@ bfc_status gemm(int64_t M, int64_t N, int64_t K, Operand A, Operand B, const flo
     set_error("bfc_mlp: matrix too large for one launch");
     return BFC_EINVAL;
   }
-  gemm_kernel<TI><<<dim3((unsigned)gx, (unsigned)gy), 256, 0, st>>>(M, N, K, A, B, bias, act, C,
-                                                                     Ch, ldc);
+  // few output tiles over a long reduction: split k so the launch fills the
+  // GPU, chunks a multiple of the slab, partial tiles summed in order
+  int64_t split = 1;
+  if (gx * gy < kSplitTarget && K >= 2 * kMinChunk)
+    split = std::min((kSplitTarget + gx * gy - 1) / (gx * gy), K / kMinChunk);
+  if (split > 1) {
+    int64_t kc = (K + split - 1) / split;
+    kc = (kc + kSlab - 1) / kSlab * kSlab;
+    split = (K + kc - 1) / kc;
+    float* ws = nullptr;
+    BFC_TRY(splitk_workspace((size_t)(split * M * N), &ws));
+    gemm_kernel<TI><<<dim3((unsigned)gx, (unsigned)gy, (unsigned)split), 256, 0, st>>>(
+        M, N, K, kc, A, B, nullptr, 0, ws, nullptr, N);
+    BFC_HIP_TRY(hipGetLastError());
+    splitk_reduce_kernel<<<blocks_for(M * N, 256), 256, 0, st>>>(M, N, (int)split, ws, bias, act,
+                                                                 C, Ch, ldc);
+    BFC_HIP_TRY(hipGetLastError());
+    return BFC_OK;
+  }
+  gemm_kernel<TI><<<dim3((unsigned)gx, (unsigned)gy), 256, 0, st>>>(M, N, K, K, A, B, bias, act,
+                                                                     C, Ch, ldc);
   BFC_HIP_TRY(hipGetLastError());
   return BFC_OK;
 }

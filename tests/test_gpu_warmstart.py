@@ -22,7 +22,11 @@ from workloads import green_line_entries, random_cores, sample_pairs
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-SHAPES = [(37, 70, 131), (5, 4099, 512), (1, 512, 2000), (64, 64, 64), (65, 17, 3)]
+# (m, k, n); the products with few output tiles over a long reduction are
+# split over k: the forward of (5, 4099, 512) and the input gradient of
+# (32, 64, 20000)
+SHAPES = [(37, 70, 131), (5, 4099, 512), (1, 512, 2000), (64, 64, 64), (65, 17, 3),
+          (32, 64, 20000)]
 
 
 def _rand(shape, seed, scale=1.0):
@@ -209,18 +213,20 @@ def test_loss_gradient_batch_equals_single_calls(prec):
 
 
 def test_trained_network_beats_the_lowrank_guess_and_random_starts():
-    """A short training run (128 completions, 10 epochs) already lowers the
-    training loss and, on 12 held-out operators, needs fewer sweeps to test
-    error 1e-3 on average than the Sec. 5.2 initial guess and than random
-    starts (a miss counts as the 150-sweep cap); with the guess as the
-    fallback it misses no more instances than either."""
+    """A training run of 512 completions and 60 epochs (a quarter of the
+    bench's) lowers the training loss and, on 24 held-out operators, needs
+    fewer sweeps to test error 1e-3 on average than the Sec. 5.2 initial
+    guess and than random starts (a miss counts as the 150-sweep cap); with
+    the guess as the fallback it misses no more instances than either.  At
+    128 completions and 10 epochs the learned and random starts were within
+    one sweep of each other either way, depending on the held-out set."""
     from paper_2510_17734_amd import warmstart as ws
-    ds, lp, central = ws.make_dataset(128, 1000, device=DEV)
+    ds, lp, central = ws.make_dataset(512, 1000, device=DEV)
     net = ws.WarmStartNet(ws.N_FEATURES, central.numel(), out_bias=central, device=DEV)
-    hist = ws.train(net, ds, lp, epochs=10)
+    hist = ws.train(net, ds, lp, epochs=60)
     lp.close()
-    assert hist[-1] < 0.9 * hist[0], hist
-    summ = ws.summarize(ws.evaluate(net, list(range(900000, 900012)), device=DEV,
+    assert hist[-1] < 0.2 * hist[0], hist
+    summ = ws.summarize(ws.evaluate(net, list(range(900000, 900024)), device=DEV,
                                     starts=("learned", "lowrank", "random", "learned+fallback")))
     learned = summ["learned"]["mean_sweeps_capped"]
     assert learned < summ["lowrank"]["mean_sweeps_capped"], summ
