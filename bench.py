@@ -1001,7 +1001,7 @@ def main():
                 "train_loss_first_epoch": hist[0], "train_loss_last_epoch": hist[-1],
                 "target_test_err": 1e-3, "max_sweeps": 150, "starts": summ,
                 "batched_chunks_of_50": batched,
-                "complex64_vs_complex128": prec,
+                "complex64_vs_fp64": prec,
                 "sweeps_ratio_lowrank_over_learned": gain,
                 "sweeps_ratio_random_over_learned": gain_random,
                 "fallback": "learned+fallback: the Sec. 5.2 guess is swept too when the "
