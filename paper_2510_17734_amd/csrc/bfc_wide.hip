@@ -23,7 +23,7 @@ namespace {
 //   LDS; each lane accumulates its share of the r(r+1)/2 entries of the lower
 //   triangle of K = sum conj(a_e) a_e^T and of h = sum conj(a_e) t_e; the
 //   regularized system is factored column by column in LDS by the wavefront.
-// * inner cores: one 256-thread workgroup per slice, Gram and solve fused.
+// * inner cores: one workgroup per slice, Gram and solve fused.  With
 //   1024 threads per slice: batches of 16 subgroups are gathered by one
 //   wavefront each, which also forms the subgroup's real-coordinate rows (as
 //   in the one-wavefront kernel); the 16 wavefronts take the MFMA tiles of
