@@ -29,10 +29,12 @@ namespace {
 //   in the one-wavefront kernel); the 16 wavefronts take the MFMA tiles of
 //   S = A^T B in turn, and only the tiles the system reads are computed (the
 //   K block and the right-hand-side corner).  S goes to the slice's region
-//   of device memory (it does not fit in LDS at r = 12), the bordered system
-//   is assembled from it into registers over a 32 x 32 thread grid and
-//   factored there (reg_cholesky); the factor's rows replace S in the region,
-//   and a second launch back-substitutes with one wavefront per slice.
+//   of device memory (it does not fit in LDS at r = 12); the bordered system
+//   is assembled from it into registers over a thread grid and factored
+//   there (reg_cholesky): at r <= 11 by a launch of its own over a 16 x 16
+//   grid, at r = 12 by the same workgroup over a 32 x 32 grid (WideGeom).
+//   The factor's rows replace S in the region, and a last launch
+//   back-substitutes with one wavefront per slice.
 // ---------------------------------------------------------------------------
 constexpr int kWideSub = 16;       // subgroups per batch of the fused inner kernel
 constexpr int kWideThreads = 1024;  // threads of the fused inner kernel
@@ -49,7 +51,13 @@ struct WideGeom {
   static constexpr int WP = (W + 15) / 16 * 16;
   static constexpr int NB = WP / 16;
   static constexpr int LDW = WP + 1;          // padded LDS row
-  static constexpr int G = 32;                // factorization grid: G x G threads
+  // The factorization runs in a launch of its own over a 16 x 16 thread grid
+  // (four wavefronts, one per SIMD, up to 512 registers a lane) where that
+  // leaves two workgroups per CU (r <= 11: at most 230 registers); at r = 12
+  // it needs 316, one workgroup per CU, and runs faster inside the Gram's
+  // 1024-thread workgroup over a 32 x 32 grid.
+  static constexpr bool SPLIT = R <= 11;
+  static constexpr int G = SPLIT ? 16 : 32;   // factorization grid: G x G threads
   static constexpr int NS = RegGrid<D, G>::NS;
   static constexpr size_t S_BYTES = (size_t)WP * WP * 8;
   static constexpr size_t F_BYTES = (size_t)D * (D + 1) / 2 * 16;
@@ -252,13 +260,15 @@ __global__ __launch_bounds__(64) void outer_wide_kernel(WideOuterArgs<T> A) {
 // The slice's subgroups are those of its work items (one item per slice at
 // these ranks), summed in subgroup order, so results do not depend on
 // scheduling.
+template <typename T, int R>
+__device__ void factor_slice(const WideArgs<T>& A, int tile, double* S);
+
 template <typename T, int R, int BYROW>
 __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A) {
   typedef WideGeom<R> G;
   constexpr int D = G::D, W = G::W, WP = G::WP, NB = G::NB, LDW = G::LDW;
-  constexpr int GG = G::G, NS = G::NS, NT = kWideThreads, NW = NT / 64;
+  constexpr int NT = kWideThreads, NW = NT / 64;
   constexpr int NTILE = wide_tiles<R>(), TPW = (NTILE + NW - 1) / NW;
-  static_assert(GG * GG == NT, "factorization grid");
   static_assert(kWideSub == NW, "one wavefront per subgroup of a batch");
   typedef Mfma<double>::acc_t acc_t;  // the Gram in FP64 in both precisions
   __shared__ cx<T> us[kWideSub][R];              // each subgroup's shared environment
@@ -266,12 +276,8 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
   __shared__ cx<T> ts[kWideSub][kSubgroup];      // its entries' values
   __shared__ double As[kWideSub * LDW];
   __shared__ double Bs[kWideSub * LDW];
-  __shared__ double2 col[2 * (D + 1)];
-  __shared__ double2 hb[D];
-  __shared__ double2 ob[D];
-  __shared__ double dg[D];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
   const int it0 = A.tile_items[tile], it1 = A.tile_items[tile + 1];
   if (it0 == it1) return;  // no observed entry in this slice: keep it
@@ -378,10 +384,35 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
         const int cl = ty[q] * 16 + (lane & 15);
         S[row * WP + cl] = acc[q][v];
       }
-  // S passes between the workgroup's threads through device memory; the
-  // workgroup barrier orders it (one CU, one L1 and L2: no device-scope
-  // fence, which on this chip writes back and invalidates the XCD's L2)
-  __syncthreads();
+  if constexpr (!G::SPLIT) {
+    static_assert(G::G * G::G == NT, "the fused factorization's grid is the workgroup");
+    // S passes between the workgroup's threads through device memory; the
+    // workgroup barrier orders it (one CU, one L1 and L2: no device-scope
+    // fence, which on this chip writes back and invalidates the XCD's L2)
+    __syncthreads();
+    factor_slice<T, R>(A, tile, S);
+  }
+}
+
+// The bordered system of one slice (blockIdx -> slice) assembled from its
+// Gram S in the slice's region into registers over a 16 x 16 thread grid
+// and factored there (reg_cholesky, one column per barrier of the grid's
+// four wavefronts, one per SIMD); the regularization ladder re-reads S.
+// The bordered system of a slice assembled from its Gram S (in the slice's
+// region) into registers over the G x G grid of the calling threads and
+// factored there (reg_cholesky, one column per barrier); the
+// regularization ladder re-reads S.  Leaves the factor's rows, w and the
+// status over S for the back substitution.  Every thread of the workgroup
+// calls it (the grid is the whole workgroup).
+template <typename T, int R>
+__device__ void factor_slice(const WideArgs<T>& A, int tile, double* S) {
+  typedef WideGeom<R> G;
+  constexpr int D = G::D, WP = G::WP, GG = G::G, NS = G::NS, NT = GG * GG;
+  __shared__ double2 col[2 * (D + 1)];
+  __shared__ double2 hb[D];
+  __shared__ double2 ob[D];
+  __shared__ double dg[D];
+  const int tid = threadIdx.x;
   cx<T>* slice = A.slices + (int64_t)tile * D;
   for (int i = tid; i < D; i += NT) {
     dg[i] = inner_K<R>(S, WP, i, i).x;
@@ -456,6 +487,16 @@ __global__ __launch_bounds__(kWideThreads) void inner_wide_kernel(WideArgs<T> A)
       if (i < D && j <= i) F[i * (i + 1) / 2 + j] = make_double2(mr[ia][jc], mi[ia][jc]);
       if (i == D && j < D) Wv[j] = make_double2(mr[ia][jc], -mi[ia][jc]);
     }
+}
+
+// The factorization as a launch of its own (ranks with G::SPLIT).
+template <typename T, int R>
+__global__ __launch_bounds__(WideGeom<R>::G * WideGeom<R>::G) void wide_factor_kernel(
+    WideArgs<T> A) {
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int it0 = A.tile_items[tile], it1 = A.tile_items[tile + 1];
+  if (it0 == it1) return;  // no observed entry in this slice: keep it
+  factor_slice<T, R>(A, tile, (double*)(A.region + (size_t)it0 * WideGeom<R>::REGION));
 }
 
 // Back substitution L^H s = w of every factored slice, one wavefront per
@@ -565,6 +606,10 @@ bfc_status launch_inner_wide(const WideArgs<T>& a, int nslices, int by_row, hipS
     else
       inner_wide_kernel<T, R, 0><<<nslices, kWideThreads, 0, st>>>(a);
     BFC_HIP_TRY(hipGetLastError());
+    if constexpr (WideGeom<R>::SPLIT) {
+      wide_factor_kernel<T, R><<<nslices, WideGeom<R>::G * WideGeom<R>::G, 0, st>>>(a);
+      BFC_HIP_TRY(hipGetLastError());
+    }
     wide_backsub_kernel<T, R><<<nslices, 64, 0, st>>>(a);
   }
   BFC_HIP_TRY(hipGetLastError());
