@@ -27,7 +27,8 @@ def _parts(n, L, r, nnz, seed=3):
 
 @pytest.mark.parametrize("shape", [(256, 4, 4, 8155, "c128"), (192, 4, 3, 5000, "c64"),
                                    (96, 0, 3, 2000, "c128"), (128, 5, 8, 6000, "bf16gram"),
-                                   (64, 6, 2, 4000, "c64")],
+                                   (64, 6, 2, 4000, "c64"), (256, 6, 10, 30000, "c64"),
+                                   (256, 6, 12, 30000, "c128")],
                          ids=lambda s: "n%d_L%d_r%d_%s" % (s[0], s[1], s[2], s[4]))
 def test_layout_validates(shape):
     n, L, r, nnz, prec = shape
@@ -41,7 +42,7 @@ def test_layout_validates(shape):
     bfc.validate(prob)
     bfc.sweep(prob)
     bfc.validate(prob)
-    if L >= 1:
+    if L >= 1 and r <= 8:  # one work item per slice above rank 8
         bfc.set_item_size(prob, 64)  # work items rebuilt
         bfc.validate(prob)
     prob.close()
@@ -60,12 +61,15 @@ def _free_bytes():
     return torch.cuda.mem_get_info()[0]
 
 
-def test_out_of_memory_at_every_allocation_of_init():
-    n, L, r, nnz = 256, 4, 4, 8155
+@pytest.mark.parametrize("shape", [(256, 4, 4, 8155, "bf16gram"), (256, 6, 11, 30000, "c64")],
+                         ids=lambda s: "r%d_%s" % (s[2], s[4]))
+def test_out_of_memory_at_every_allocation_of_init(shape):
+    # the second case: the wide ranks' per-slice regions
+    n, L, r, nnz, prec = shape
     rows, cols, vals, cores = _parts(n, L, r, nnz)
     rows, cols, vals = (torch.as_tensor(a, device=DEV) for a in (rows, cols, vals))
     cores = torch.as_tensor(bfc.flatten_cores(cores), device=DEV)
-    cfg = bfc.Config(n=n, L=L, r=r, precision="bf16gram")
+    cfg = bfc.Config(n=n, L=L, r=r, precision=prec)
     ok = bfc.init_cores(cfg, rows, cols, vals, cores, device=DEV)  # warm the runtime up
     ok.close()
     before = _free_bytes()
