@@ -935,8 +935,44 @@ def main():
                 "ms_per_iteration": round(1e3 * spent / iters, 4),
                 "entries_per_s": round(w.nnz * iters / spent, 1), **errs}
 
+    def adam_alpha_record(name, alphas=(3e-3, 1e-2, 3e-2), iters=1000):
+        """ADAM on another workload at several learning rates (the paper
+        gives none): test error at 20, 60, 200 and `iters` iterations, the
+        iterations to reach the ALS run's test error after 20 sweeps, and the
+        lowest test error seen, each from the workload's random start."""
+        wa = make_workload(name)
+        mk = lambda: bfc.init_cores(bfc.Config(n=wa.n, L=wa.L, r=wa.r, precision="c64"),
+                                    wa.rows, wa.cols, wa.vals, wa.cores0, device=dev)
+        pa = mk()
+        for _ in range(20):
+            bfc.sweep(pa)
+        als20 = bfc.relative_error(pa, wa.test_rows, wa.test_cols, wa.test_vals)
+        pa.close()
+        rec = {"workload": wa.name, "precision": "c64", "als_test_err_at_20_sweeps": als20,
+               "by_alpha": {}}
+        marks = (20, 60, 200, iters)
+        for a in alphas:
+            pa = mk()
+            r_ = {"iters_to_als_20": None, "best_test_err": float("inf")}
+            for t in range(1, iters + 1):
+                bfc.adam_sweep(pa, t, alpha=a)
+                if t % 10 == 0 or t in marks:
+                    e = bfc.relative_error(pa, wa.test_rows, wa.test_cols, wa.test_vals)
+                    if not math.isfinite(e):
+                        r_["diverged_at"] = t
+                        break
+                    r_["best_test_err"] = min(r_["best_test_err"], e)
+                    if t in marks:
+                        r_[f"test_err_at_{t}"] = e
+                    if r_["iters_to_als_20"] is None and e <= als20:
+                        r_["iters_to_als_20"] = t
+            pa.close()
+            rec["by_alpha"][f"{a:g}"] = r_
+        return rec
+
     if not args.no_adam:
         out["adam"] = adam_record()
+        out["adam"]["green-line-256"] = adam_alpha_record("green-line-256")
 
     def adf_record(iters=60):
         """Alg. "ADF for Butterfly Completion" from the same random start: time
