@@ -71,6 +71,7 @@ __host__ __device__ inline void cfma_conj(cx<T>& acc, cx<T> a, cx<T> b) {
 // Entries per subgroup: runs of one inner slice's row (or column) are cut into
 // pieces of at most this many entries, one lane each in the Gram kernel.
 constexpr int kSubgroup = 8;
+constexpr int kSubRec = 4 + kSubgroup;  // int32 values per subgroup record
 
 // Highest rank of the one-wavefront kernels and of every call of the library;
 // ranks kNarrowRank+1 .. BFC_MAX_RANK have the sweep, reconstruction and
@@ -95,6 +96,12 @@ struct CoreLayout {
   int32_t nruns = 0;           // distinct (slice, row|column) pairs with entries
   int32_t nsub = 0;
   int32_t* sub_off = nullptr;  // nsub + 1
+  // nsub records of kSubRec values, read by the FP32 / FP64 Gram at ranks
+  // <= kNarrowRank (null otherwise): first entry, entry count, the node of
+  // the environment the subgroup shares, 0, then the node of the other
+  // environment for each of its kSubgroup entries (-1 past the count), so a
+  // lane has all of a subgroup's indices after one round of loads
+  int32_t* sub_rec = nullptr;
   int32_t nitems = 0;
   WorkItem* items = nullptr;
   int32_t* tile_items = nullptr;  // nblocks + 1: item range of each slice

@@ -117,6 +117,23 @@ __global__ void sub_offsets_kernel(const int32_t* subhead, const int32_t* sub_id
   if (k == nnz - 1) sub_off[nsub] = (int32_t)nnz;
 }
 
+// Subgroup records (CoreLayout::sub_rec): shared_idx names the environment
+// node the subgroup's entries share (the left one when grouped by row),
+// vary_idx the node of the other environment of every entry.
+__global__ void sub_records_kernel(const int32_t* sub_off, int32_t nsub, const int32_t* shared_idx,
+                                   const int32_t* vary_idx, int32_t* rec) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsub) return;
+  const int32_t e0 = sub_off[s], e1 = sub_off[s + 1];
+  int32_t* o = rec + s * kSubRec;
+  o[0] = e0;
+  o[1] = e1 - e0;
+  o[2] = shared_idx[e0];
+  o[3] = 0;
+#pragma unroll
+  for (int q = 0; q < kSubgroup; ++q) o[4 + q] = (e0 + q < e1) ? vary_idx[e0 + q] : -1;
+}
+
 __global__ void tile_subs_kernel(const int32_t* blk_off, const int32_t* sub_id, int64_t nnz,
                                  int nb, int32_t nsub, int32_t* tile_sub) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -414,6 +431,15 @@ bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols
     C.nruns = last[2] + last[3];
     BFC_TRY(dev_alloc(P, (void**)&C.sub_off, ((int64_t)C.nsub + 1) * 4));
     sub_offsets_kernel<<<grid_for(nnz), 256, 0, st>>>(idx, tmp2, nnz, C.nsub, C.sub_off);
+    if (P->r <= kNarrowRank && P->prec != BFC_C64_BF16GRAM) {
+      // the environment indices the Gram reads: a row of Z^1 at p = 1, a
+      // column of Z^(L+2) at p = L, cached trie nodes otherwise
+      const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
+      const int32_t* ridx = (p == L) ? C.cols : C.rnode;
+      BFC_TRY(dev_alloc(P, (void**)&C.sub_rec, (int64_t)C.nsub * kSubRec * 4));
+      sub_records_kernel<<<grid_for(C.nsub), 256, 0, st>>>(
+          C.sub_off, C.nsub, C.group_by_row ? lidx : ridx, C.group_by_row ? ridx : lidx, C.sub_rec);
+    }
     int32_t* tile_sub = head;  // reuse: nblocks + 1 <= nnz is not guaranteed, size check
     if ((int64_t)C.nblocks + 1 > nnz) BFC_HIP_TRY(S.get((void**)&tile_sub, (C.nblocks + 1) * 4));
     tile_subs_kernel<<<grid_for(C.nblocks + 1), 256, 0, st>>>(C.blk_off, tmp2, nnz, C.nblocks,

@@ -389,10 +389,13 @@ struct InnerGeom {
 // A = [sum Rl | Re w | -Im w], B = [Rrho | Re rho | -Im rho], w = sum conj(l) t:
 // the imaginary parts are negated so that the right-hand side reads the same
 // way as in the row case.
+// The same from indices already in registers: `shared` is the node of the
+// environment the subgroup's entries share (left when BYROW), id[q] the node
+// of the other environment of entry e0 + q (-1 from e1 on).
 template <typename T, int R, int BYROW>
-__device__ __attribute__((always_inline)) inline void subgroup_rows(
-    bool live, int e0, int e1, const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv,
-    const int32_t* ridx, const cx<T>* vals, T (&arow)[InnerGeom<R>::W],
+__device__ __attribute__((always_inline)) inline void subgroup_rows_ids(
+    bool live, int e0, int e1, int shared, const int (&id)[kSubgroup], const cx<T>* lenv,
+    const cx<T>* renv, const cx<T>* vals, T (&arow)[InnerGeom<R>::W],
     T (&brow)[InnerGeom<R>::W]) {
   constexpr int D = R * R;
   constexpr int GG = gram_gather_group(R, sizeof(T));
@@ -406,19 +409,9 @@ __device__ __attribute__((always_inline)) inline void subgroup_rows(
     yx[k] = yy[k] = T(0);
     shared_env[k] = cx<T>{T(0), T(0)};
   }
-  if (live) {
-    if (BYROW)
-      load_env<T, R>(lenv, lidx[e0], shared_env);
-    else
-      load_env<T, R>(renv, ridx[e0], shared_env);
-  }
+  if (live) load_env<T, R>(BYROW ? lenv : renv, shared, shared_env);
   {
-    // a subgroup holds at most kSubgroup entries: every index load first
-    const int32_t* eidx = BYROW ? ridx : lidx;
     const cx<T>* esrc = BYROW ? renv : lenv;
-    int id[kSubgroup];
-#pragma unroll
-    for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
     // entries in groups of G whose vector loads are issued together; a group
     // that no lane of the wavefront needs is skipped
 #pragma unroll
@@ -471,14 +464,29 @@ __device__ __attribute__((always_inline)) inline void subgroup_rows(
   }
 }
 
+// The A and B rows of one subgroup from the per-entry index arrays (lidx and
+// ridx name each sorted entry's left and right environment source).
+template <typename T, int R, int BYROW>
+__device__ __attribute__((always_inline)) inline void subgroup_rows(
+    bool live, int e0, int e1, const cx<T>* lenv, const int32_t* lidx, const cx<T>* renv,
+    const int32_t* ridx, const cx<T>* vals, T (&arow)[InnerGeom<R>::W],
+    T (&brow)[InnerGeom<R>::W]) {
+  // a subgroup holds at most kSubgroup entries: every index load first
+  const int32_t* eidx = BYROW ? ridx : lidx;
+  int shared = 0;
+  if (live) shared = BYROW ? lidx[e0] : ridx[e0];
+  int id[kSubgroup];
+#pragma unroll
+  for (int q = 0; q < kSubgroup; ++q) id[q] = (e0 + q < e1) ? eidx[e0 + q] : -1;
+  subgroup_rows_ids<T, R, BYROW>(live, e0, e1, shared, id, lenv, renv, vals, arow, brow);
+}
+
 template <typename T>
 struct GramArgs {
   const cx<T>* lenv;
-  const int32_t* lidx;
   const cx<T>* renv;
-  const int32_t* ridx;
   const cx<T>* vals;
-  const int32_t* sub_off;
+  const int4* sub_rec;  // kSubRec / 4 int4 per subgroup (CoreLayout::sub_rec)
   const WorkItem* items;
   T* partials;
 };
@@ -486,11 +494,9 @@ struct GramArgs {
 template <typename T, int R, int BYROW>
 __device__ __attribute__((always_inline)) inline void inner_gram_body(const GramArgs<T>& A, int blk) {
   const cx<T>* lenv = A.lenv;
-  const int32_t* lidx = A.lidx;
   const cx<T>* renv = A.renv;
-  const int32_t* ridx = A.ridx;
   const cx<T>* vals = A.vals;
-  const int32_t* sub_off = A.sub_off;
+  const int4* sub_rec = A.sub_rec;
   const WorkItem* items = A.items;
   T* partials = A.partials;
 
@@ -514,13 +520,23 @@ __device__ __attribute__((always_inline)) inline void inner_gram_body(const Gram
   for (int base = it.sub0; base < it.sub1; base += 64) {
     const int s = base + lane;
     const bool live = s < it.sub1;
-    int e0 = 0, e1 = 0;
+    // the subgroup's whole record in one round of loads (no offset first)
+    int e0 = 0, cnt = 0, shared = 0;
+    int id[kSubgroup];
+#pragma unroll
+    for (int q = 0; q < kSubgroup; ++q) id[q] = -1;
     if (live) {
-      e0 = sub_off[s];
-      e1 = sub_off[s + 1];
+      static_assert(kSubRec == 12 && kSubgroup == 8, "record layout");
+      const int4* rp = sub_rec + (int64_t)s * (kSubRec / 4);
+      const int4 h = rp[0], i0 = rp[1], i1 = rp[2];
+      e0 = h.x;
+      cnt = h.y;
+      shared = h.z;
+      id[0] = i0.x; id[1] = i0.y; id[2] = i0.z; id[3] = i0.w;
+      id[4] = i1.x; id[5] = i1.y; id[6] = i1.z; id[7] = i1.w;
     }
     T a[G::W], b[G::W];
-    subgroup_rows<T, R, BYROW>(live, e0, e1, lenv, lidx, renv, ridx, vals, a, b);
+    subgroup_rows_ids<T, R, BYROW>(live, e0, e0 + cnt, shared, id, lenv, renv, vals, a, b);
 #pragma unroll
     for (int ph = 0; ph < PH; ++ph) {
       if (lane / RP == ph) {
@@ -1529,10 +1545,10 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
       if (!bf16) {
         if (C.group_by_row)
           inner_gram_kernel<T, R, 1><<<C.nitems, 64, 0, st>>>(GramArgs<T>{
-              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials});
+              lenv, renv, (const cx<T>*)C.vals, (const int4*)C.sub_rec, C.items, (T*)P->partials});
         else
           inner_gram_kernel<T, R, 0><<<C.nitems, 64, 0, st>>>(GramArgs<T>{
-              lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items, (T*)P->partials});
+              lenv, renv, (const cx<T>*)C.vals, (const int4*)C.sub_rec, C.items, (T*)P->partials});
       }
       BFC_HIP_TRY(hipGetLastError());
     }
@@ -2469,11 +2485,9 @@ struct BatchStep {
     const CoreLayout& C = P->lay[p];
     cx<T>* cores = (cx<T>*)P->cores;
     const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R) : (const cx<T>*)P->rlev[p].vec;
-    const int32_t* ridx = (p == L) ? C.cols : C.rnode;
     const cx<T>* lenv = (p == 1) ? cores : (const cx<T>*)P->llev[p].vec;
-    const int32_t* lidx = (p == 1) ? C.rows : C.lnode;
     if (C.nitems > 0) {
-      GramArgs<T> g{lenv, lidx, renv, ridx, (const cx<T>*)C.vals, C.sub_off, C.items,
+      GramArgs<T> g{lenv, renv, (const cx<T>*)C.vals, (const int4*)C.sub_rec, C.items,
                     (T*)P->partials};
       if (C.group_by_row) {
         grow.push_back(g);

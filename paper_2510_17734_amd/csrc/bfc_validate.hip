@@ -180,6 +180,32 @@ bfc_status bfc_validate(const bfc_problem* p) {
           return bad("subgroup mixes rows (or columns)" + at(q, e));
       if (C.tile_sub[b] > s || C.tile_sub[b + 1] <= s) return bad("slice subgroup range" + at(q, e0));
     }
+    // subgroup records of the narrow-rank FP32 / FP64 Gram: offsets and
+    // environment indices as the per-entry arrays give them
+    if (C.sub_rec) {
+      std::vector<int32_t> rec, ln, rn;
+      BFC_TRY(fetch(rec, C.sub_rec, (int64_t)C.nsub * kSubRec));
+      if (q >= 2) BFC_TRY(fetch(ln, C.lnode, nnz));
+      if (q <= L - 1) BFC_TRY(fetch(rn, C.rnode, nnz));
+      // the index the Gram reads: a row of Z^1 at q = 1, a column of
+      // Z^(L+2) at q = L, a trie node otherwise
+      auto lsrc = [&](int64_t e) { return q == 1 ? rows[e] : ln[e]; };
+      auto rsrc = [&](int64_t e) { return q == L ? cols[e] : rn[e]; };
+      for (int64_t s = 0; s < C.nsub; ++s) {
+        const int32_t* o = rec.data() + s * kSubRec;
+        const int64_t e0 = so[s], e1 = so[s + 1];
+        if (o[0] != e0 || o[1] != e1 - e0) return bad("subgroup record offsets" + at(q, e0));
+        if (o[2] != (C.group_by_row ? lsrc(e0) : rsrc(e0)))
+          return bad("subgroup record shared node" + at(q, e0));
+        for (int k = 0; k < kSubgroup; ++k) {
+          const int64_t e = e0 + k;
+          const int32_t want = e < e1 ? (C.group_by_row ? rsrc(e) : lsrc(e)) : -1;
+          if (o[4 + k] != want) return bad("subgroup record entry node" + at(q, e0));
+        }
+      }
+    } else if (P->r <= kNarrowRank && P->prec != BFC_C64_BF16GRAM) {
+      return bad("subgroup records missing" + at(q, 0));
+    }
     if (ti[0] != 0 || ti[C.nblocks] != C.nitems) return bad("items do not span the slices" + at(q, 0));
     for (int64_t t = 0; t < C.nblocks; ++t) {
       int64_t next = C.tile_sub[t];
