@@ -37,7 +37,6 @@ __device__ inline int xcd_swizzle(int bid, int nblocks) {
   return start + q;
 }
 
-// v <- the R-vector at src + idx * R
 // Work of one launch split into tasks (one per instance of a batch): a
 // batched kernel reads its task's arguments from `tasks` and its block index
 // within the task from the prefix table `block_off` (ntasks + 1 entries).
@@ -54,11 +53,24 @@ __device__ __attribute__((always_inline)) inline int find_task(const int32_t* bl
   return lo;
 }
 
-template <typename T, int R>
+// v <- the R-vector at src + idx * R.  WIDE: two complex64 values per
+// 16-byte load where R is even (the vectors then start on 16-byte
+// boundaries); it costs registers, so only kernels with room use it.
+template <typename T, int R, bool WIDE = false>
 __device__ inline void load_env(const cx<T>* __restrict__ src, int idx, cx<T> (&v)[R]) {
   const cx<T>* p = src + (int64_t)idx * R;
+  if constexpr (WIDE && sizeof(T) == 4 && R % 2 == 0) {
+    const float4* q = reinterpret_cast<const float4*>(p);
 #pragma unroll
-  for (int a = 0; a < R; ++a) v[a] = p[a];
+    for (int k = 0; k < R / 2; ++k) {
+      const float4 t = q[k];
+      v[2 * k] = cx<T>{t.x, t.y};
+      v[2 * k + 1] = cx<T>{t.z, t.w};
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < R; ++a) v[a] = p[a];
+  }
 }
 
 // Marks a loaded value as used here.  Placed after a group of loads, it keeps
@@ -73,13 +85,13 @@ __device__ __attribute__((always_inline)) inline void pin(cx<T>& v) {
 // Environment vectors and values of G entries, loaded as one group.  An absent
 // entry (id < 0) reads vector 0 and value 0 (both exist whenever the kernel
 // runs) and must be skipped by the caller.
-template <typename T, int R, int G>
+template <typename T, int R, int G, bool WIDE = false>
 __device__ __attribute__((always_inline)) inline void gather_group(
     const cx<T>* __restrict__ src, const cx<T>* __restrict__ vals, const int (&id)[G],
     const int (&ent)[G], cx<T> (&v)[G][R], cx<T> (&t)[G]) {
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    load_env<T, R>(src, id[g] >= 0 ? id[g] : 0, v[g]);
+    load_env<T, R, WIDE>(src, id[g] >= 0 ? id[g] : 0, v[g]);
     t[g] = vals[id[g] >= 0 ? ent[g] : 0];
   }
 #pragma unroll

@@ -264,7 +264,7 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
       id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
     }
     cx<T> v[4][R], t[4];
-    gather_group<T, R, 4>(env, vals, id, ent, v, t);
+    gather_group<T, R, 4, true>(env, vals, id, ent, v, t);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (id[q] < 0) continue;
@@ -314,7 +314,7 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
       id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
     }
     cx<T> vv[4][R], tt[4];
-    gather_group<T, R, 4>(env, vals, id, ent, vv, tt);
+    gather_group<T, R, 4, true>(env, vals, id, ent, vv, tt);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (id[q] < 0) continue;
