@@ -110,11 +110,13 @@ def sweep_model(stats, w, cbytes, env_total):
     return m
 
 
-def implementation_bytes(stats, w, cbytes, env_total):
+def implementation_bytes(stats, w, cbytes, env_total, records=True):
     """Bytes one sweep's kernels must move in this implementation, every
     array once (entry values and indices, environment vectors and core rows
     read, Gram partial products written and read), per kernel kind: the
-    yardstick the counter traffic is compared with."""
+    yardstick the counter traffic is compared with.  records: the Gram reads
+    each subgroup's 48-byte index record (complex64 and complex128 at
+    r <= 8) instead of subgroup offsets and two node indices per entry."""
     r, n, L, nnz = w.r, w.n, w.L, w.nnz
     d = r * r
     wp = (d + 2 * r + 15) // 16 * 16
@@ -126,8 +128,8 @@ def implementation_bytes(stats, w, cbytes, env_total):
         st = stats[p]
         lnodes = st["left_env_nodes"] or n   # rows of Z^1 when p = 1
         rnodes = st["right_env_nodes"] or n  # rows of Z^(L+2) when p = L
-        gb += nnz * (cbytes + 8) + (lnodes + rnodes) * vec + st["subgroups"] * 4 \
-            + st["items"] * wp * wp * real
+        index = st["subgroups"] * 48 if records else nnz * 8 + st["subgroups"] * 4
+        gb += nnz * cbytes + index + (lnodes + rnodes) * vec + st["items"] * wp * wp * real
         sb += st["items"] * wp * wp * real + 2 * st["blocks"] * d * cbytes
     m["inner_gram"] = gb
     m["inner_solve"] = sb
@@ -643,7 +645,7 @@ def main():
     cbytes = 8 if args.precision == "c64" else 16
     env_total = bfc.env_nodes(prob)
     models = sweep_model(stats, w, cbytes, env_total)
-    impl = implementation_bytes(stats, w, cbytes, env_total)
+    impl = implementation_bytes(stats, w, cbytes, env_total, records=w.r <= WIDE_RANK)
     # environment dispatches per sweep: the top four right levels share one
     # launch, every other level has its own
     env_levels = sum(1 for q in range(w.L - 4) if stats[q]["right_env_nodes"]) + \
@@ -673,7 +675,7 @@ def main():
         "unit": unit,
         "frac": round(achieved / peak, 5),
         "traffic": traffic,
-        "traffic_over_algorithmic_bytes": round(traffic / dbytes, 3) if traffic else None,
+        "traffic_over_algorithmic_bytes": round(traffic / dbytes, 3) if traffic and dbytes else None,
         "algorithmic_bytes_per_launch": round(dbytes),
         "algorithmic_flops_per_launch": round(dflops),
         "hbm_frac": round(dbytes / t_launch / 1e9 / PEAKS["hbm_GBs"], 5),
