@@ -111,6 +111,12 @@ struct CoreLayout {
   // a row of Z^1 or of Z^(L+2) itself)
   int32_t* lnode = nullptr;
   int32_t* rnode = nullptr;
+  // outer cores at L >= 2 and ranks <= kNarrowRank: for every sorted entry,
+  // 2 x its node on the trie level next to the outermost one (right level 1
+  // for core 0, left level L for core L+1) plus the bit that picks which of
+  // the fiber's two slices of the adjacent inner core (Z^2, Z^(L+1)) turns
+  // that node into the entry's environment (null otherwise)
+  int32_t* up_node = nullptr;
 };
 
 // One level of the environment trie.  Right level p (0 <= p < L) holds the

@@ -117,6 +117,17 @@ __global__ void sub_offsets_kernel(const int32_t* subhead, const int32_t* sub_id
   if (k == nnz - 1) sub_off[nsub] = (int32_t)nnz;
 }
 
+// CoreLayout::up_node of an outer core: 2 x the entry's node on the level
+// above (ent_up, input order; idx maps sorted to input positions) plus the
+// top bit of the other block index (column block for core 0, row block for
+// core L+1), which names the slice of the adjacent core.
+__global__ void up_node_kernel(const int32_t* idx, const int32_t* ent_up, const int32_t* other,
+                               int64_t nnz, int c, int L, int32_t* up) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  up[k] = 2 * ent_up[idx[k]] + (((other[k] / c) >> (L - 1)) & 1);
+}
+
 // Subgroup records (CoreLayout::sub_rec): shared_idx names the environment
 // node the subgroup's entries share (the left one when grouped by row),
 // vary_idx the node of the other environment of every entry.
@@ -411,6 +422,12 @@ bfc_status build_layout(Problem* P, const int32_t* d_rows, const int32_t* d_cols
     if (p >= 2) {
       BFC_TRY(dev_alloc(P, (void**)&C.lnode, nnz * 4));
       gather_i32_kernel<<<grid_for(nnz), 256, 0, st>>>(idx, ent_l[p], nnz, C.lnode);
+    }
+    if ((p == 0 || p == L + 1) && L >= 2 && P->r <= kNarrowRank) {
+      BFC_TRY(dev_alloc(P, (void**)&C.up_node, nnz * 4));
+      up_node_kernel<<<grid_for(nnz), 256, 0, st>>>(idx, p == 0 ? ent_r[1] : ent_l[L],
+                                                    p == 0 ? C.cols : C.rows, nnz, c, L,
+                                                    C.up_node);
     }
     BFC_HIP_TRY(hipGetLastError());
     if (!inner) continue;

@@ -226,9 +226,20 @@ struct OuterArgs {
   int prox;
   int32_t* flags;
   double* res_partial;  // per block: residual norms after the update, or null
+  // UP > 0 (see outer_update_body): the adjacent inner core, L and c
+  const cx<T>* zsl;
+  int L, c;
 };
 
-template <typename T, int R>
+// UP = 0: env holds every entry's environment vector (trie level 0 for core
+// 0, level L+1 for core L+1) and env_idx names it.  UP = 1 (core 0) or 2
+// (core L+1): env is the level above (right level 1, left level L) and
+// env_idx holds 2 x node + bit (CoreLayout::up_node); the entry's vector is
+// that node times one of the fiber's two slices of the adjacent core (Z^2
+// on the left for UP = 1, Z^(L+1) on the right for UP = 2), the product
+// that would have built the outermost level, with the same arithmetic, so
+// that level is never stored.
+template <typename T, int R, int UP = 0>
 __device__ __attribute__((always_inline)) inline void outer_update_body(const OuterArgs<T>& A, int blk) {
   cx<T>* fibers = A.fibers;
   const cx<T>* env = A.env;
@@ -255,19 +266,50 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
   for (int k = 0; k < D; ++k) acc[k] = T(0);
 #pragma unroll
   for (int k = 0; k < R; ++k) hx[k] = hy[k] = T(0);
+  // UP > 0: the fiber's two slices of the adjacent core, staged by its 16
+  // lanes (one wavefront) in LDS; the slice key is that of the outermost
+  // trie level: (ib << 1) | top bit of jb for core 0 (fiber = row i, ib =
+  // i / c), (top bit of ib << L) | jb for core L+1 (fiber = column j)
+  __shared__ cx<T> zs[UP ? kOuterThreads / 16 : 1][2][R * R];
+  const int fslot = UP ? (int)(threadIdx.x >> 4) : 0;
+  if constexpr (UP > 0) {
+    if (b < nblocks) {
+      const int64_t blk_idx = b / A.c;
+      const int64_t k0 = UP == 1 ? (blk_idx << 1) : blk_idx;
+      const int64_t k1 = UP == 1 ? (blk_idx << 1) | 1 : ((int64_t)1 << A.L) | blk_idx;
+      const cx<T>* s0 = A.zsl + k0 * (R * R);
+      const cx<T>* s1 = A.zsl + k1 * (R * R);
+      for (int e = sub; e < R * R; e += 16) {
+        zs[fslot][0][e] = s0[e];
+        zs[fslot][1][e] = s1[e];
+      }
+    }
+    wave_sync();
+  }
+  // entry q's vector from its loaded node (UP > 0), in place
+  auto lift = [&](cx<T> (&v)[R], int half) {
+    if constexpr (UP == 1) mat_vec<T, R>(zs[fslot][half], v);
+    if constexpr (UP == 2) vec_mat<T, R>(v, zs[fslot][half]);
+  };
   // four entries per lane and step, their loads issued as one group
   for (int base = e0 + sub; base < e1; base += 16 * 4) {
-    int id[4], ent[4];
+    int id[4], ent[4], half[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       ent[q] = base + 16 * q;
       id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+      half[q] = 0;
+      if (UP && id[q] >= 0) {
+        half[q] = id[q] & 1;
+        id[q] >>= 1;
+      }
     }
     cx<T> v[4][R], t[4];
     gather_group<T, R, 4, true>(env, vals, id, ent, v, t);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (id[q] < 0) continue;
+      lift(v[q], half[q]);
       herm_acc<T, R>(acc, v[q]);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
@@ -307,17 +349,23 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
   }
   double r0 = 0.0, r1 = 0.0;
   for (int base = e0 + sub; base < e1; base += 16 * 4) {
-    int id[4], ent[4];
+    int id[4], ent[4], half[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       ent[q] = base + 16 * q;
       id[q] = (ent[q] < e1) ? env_idx[ent[q]] : -1;
+      half[q] = 0;
+      if (UP && id[q] >= 0) {
+        half[q] = id[q] & 1;
+        id[q] >>= 1;
+      }
     }
     cx<T> vv[4][R], tt[4];
     gather_group<T, R, 4, true>(env, vals, id, ent, vv, tt);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (id[q] < 0) continue;
+      lift(vv[q], half[q]);
       const cx<T> t = tt[q];
       const cx<T>(&v)[R] = vv[q];
       cx<T> x = {T(0), T(0)};
@@ -348,9 +396,9 @@ __device__ __attribute__((always_inline)) inline void outer_update_body(const Ou
   }
 }
 
-template <typename T, int R>
+template <typename T, int R, int UP>
 __global__ __launch_bounds__(kOuterThreads) void outer_update_kernel(OuterArgs<T> A) {
-  outer_update_body<T, R>(A, xcd_swizzle(blockIdx.x, gridDim.x));
+  outer_update_body<T, R, UP>(A, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 template <typename T, int R>
@@ -1502,10 +1550,13 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
   const int L = P->L;
   const double floor_ = reg_floor_of(P);
   const int prox = P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0;
+  // the outer cores take their environments from the level above the
+  // outermost one when they can (up_node), which is then never built
+  const bool up = (p == 0 || p == L + 1) && C.up_node != nullptr;
   {
     ProfScope ps(&P->prof, KIND_ENV, st);
-    BFC_TRY(ensure_right<T, R>(P, p, st));
-    BFC_TRY(ensure_left<T, R>(P, p, st));
+    BFC_TRY(ensure_right<T, R>(P, up && p == 0 ? 1 : p, st));
+    BFC_TRY(ensure_left<T, R>(P, up && p == L + 1 ? L : p, st));
   }
   // environment sources of core p: cached level, or a row of Z^1 / Z^(L+2)
   const cx<T>* renv = (p == L) ? cores + last_off(P->n, L, R)
@@ -1521,9 +1572,21 @@ bfc_status sweep_core_t(Problem* P, int p, hipStream_t st) {
       ProfScope ps(&P->prof, KIND_OUTER, st);
       const unsigned grid = (unsigned)(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
       // the last core's update also leaves the train residual's per-fiber norms
-      outer_update_kernel<T, R><<<grid, kOuterThreads, 0, st>>>(OuterArgs<T>{
-          fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks, reg, floor_, prox,
-          P->flags, p == L + 1 ? P->fused_res : nullptr});
+      OuterArgs<T> oa{fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks, reg, floor_,
+                      prox, P->flags, p == L + 1 ? P->fused_res : nullptr, nullptr, L, P->c};
+      if (!up) {
+        outer_update_kernel<T, R, 0><<<grid, kOuterThreads, 0, st>>>(oa);
+      } else if (p == 0) {
+        oa.env = (const cx<T>*)P->rlev[1].vec;
+        oa.env_idx = C.up_node;
+        oa.zsl = cores + inner_off(P->n, L, R, 1);
+        outer_update_kernel<T, R, 1><<<grid, kOuterThreads, 0, st>>>(oa);
+      } else {
+        oa.env = (const cx<T>*)P->llev[L].vec;
+        oa.env_idx = C.up_node;
+        oa.zsl = cores + inner_off(P->n, L, R, L);
+        outer_update_kernel<T, R, 2><<<grid, kOuterThreads, 0, st>>>(oa);
+      }
     }
     BFC_HIP_TRY(hipGetLastError());
   } else {
@@ -2474,7 +2537,7 @@ struct BatchStep {
     a.push_back(OuterArgs<T>{fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks,
                              P->cfg.reg_rel, reg_floor_of(P),
                              P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0, P->flags,
-                             p == L + 1 ? P->fused_res : nullptr});
+                             p == L + 1 ? P->fused_res : nullptr, nullptr, L, P->c});
     b.push_back(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
   }
   static void inner(const Problem* P, int p, std::vector<GramArgs<T>>& grow,

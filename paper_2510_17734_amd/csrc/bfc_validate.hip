@@ -161,6 +161,31 @@ bfc_status bfc_validate(const bfc_problem* p) {
           return bad("entry points at the wrong left node" + at(q, e));
       }
     }
+    // outer cores: each entry's node on the level above the outermost one,
+    // and the half bit that picks the slice of the adjacent core
+    if (C.up_node) {
+      if (inner || L < 2) return bad("level-above nodes on a core without them" + at(q, 0));
+      std::vector<int32_t> up;
+      BFC_TRY(fetch(up, C.up_node, nnz));
+      for (int64_t e = 0; e < nnz; ++e) {
+        const int32_t k = up[e] >> 1, half = up[e] & 1;
+        if (q == 0) {
+          if (k < 0 || k >= P->rlev[1].count) return bad("level-above node out of range" + at(q, e));
+          if (ra[1][k] != (int32_t)((rows[e] / c) >> 1) || rb[1][k] != cols[e])
+            return bad("entry points at the wrong level-above node" + at(q, e));
+          if (half != (int32_t)(((cols[e] / c) >> (L - 1)) & 1))
+            return bad("level-above half bit" + at(q, e));
+        } else {
+          if (k < 0 || k >= P->llev[L].count) return bad("level-above node out of range" + at(q, e));
+          if (la[L][k] != (int32_t)((cols[e] / c) >> 1) || lb[L][k] != rows[e])
+            return bad("entry points at the wrong level-above node" + at(q, e));
+          if (half != (int32_t)(((rows[e] / c) >> (L - 1)) & 1))
+            return bad("level-above half bit" + at(q, e));
+        }
+      }
+    } else if ((q == 0 || q == L + 1) && L >= 2 && P->r <= kNarrowRank) {
+      return bad("level-above nodes missing" + at(q, 0));
+    }
     if (!inner) continue;
     // subgroups: at most kSubgroup entries of one slice sharing the row (or column)
     std::vector<int32_t> so, ti;
