@@ -85,6 +85,18 @@ def env_flops(env_nodes, r):
     return env_nodes * 8 * r * r
 
 
+def outer_from_level_above(w):
+    """The ALS sweep's outer-core updates form their entries' environments
+    from the trie level above the outermost one (L >= 2, r <= 8): right
+    level 0 and left level L+1 are then never built by the level kernels."""
+    return w.L >= 2 and w.r <= WIDE_RANK
+
+
+def outermost_nodes(stats, w):
+    """Nodes of right level 0 and left level L+1 (the outermost levels)."""
+    return stats[0]["right_env_nodes"] + stats[w.L + 1]["left_env_nodes"]
+
+
 def sweep_model(stats, w, cbytes, env_total):
     """Algorithmic work of one sweep per kernel kind: (bytes, flops).
 
@@ -92,7 +104,9 @@ def sweep_model(stats, w, cbytes, env_total):
     entry, attributed to the kernels that read them (the inner Grams and the
     outer updates); flops: the grouped Gram and right-hand side, the outer
     products, the slice Choleskys (4 d^3 / 3 real flops per complex d x d
-    factorization, plus the triangular solves) and the trie's mat-vecs."""
+    factorization, plus the triangular solves) and the trie's mat-vecs, one
+    per node (the outermost levels' counted with the outer updates when those
+    form them)."""
     r, L, nnz = w.r, w.L, w.nnz
     d = r * r
     eb = entry_bytes(cbytes)
@@ -106,6 +120,10 @@ def sweep_model(stats, w, cbytes, env_total):
         m["inner_gram"] = (m["inner_gram"][0], m["inner_gram"][1] + m["inner_solve"][1])
         m["inner_solve"] = (0, 0)
     m["env"] = (0, env_flops(env_total, r))
+    if outer_from_level_above(w):
+        moved = env_flops(outermost_nodes(stats, w), r)
+        m["env"] = (0, m["env"][1] - moved)
+        m["outer"] = (m["outer"][0], m["outer"][1] + moved)
     m["residual"] = (0, nnz * 8 * r)
     return m
 
@@ -134,12 +152,18 @@ def implementation_bytes(stats, w, cbytes, env_total, records=True):
     m["inner_gram"] = gb
     m["inner_solve"] = sb
     ob = 0
+    up = outer_from_level_above(w)
     for p in (0, L + 1):
         st = stats[p]
-        nodes = st["right_env_nodes"] + st["left_env_nodes"]
+        if up:  # the level above, and the adjacent core's slices
+            nodes = stats[1]["right_env_nodes"] if p == 0 else stats[L]["left_env_nodes"]
+            ob += (2 << L) * d * cbytes
+        else:
+            nodes = st["right_env_nodes"] + st["left_env_nodes"]
         ob += nnz * (cbytes + 4) + nodes * vec + 2 * n * r * cbytes + (st["blocks"] + 1) * 4
     m["outer"] = ob
-    m["env"] = env_total * (2 * vec + 12)
+    built = env_total - (outermost_nodes(stats, w) if up else 0)
+    m["env"] = built * (2 * vec + 12)
     m["residual"] = nnz * (8 + cbytes) + stats[L + 1]["left_env_nodes"] * vec + n * vec
     return m
 
@@ -651,6 +675,8 @@ def main():
     env_levels = sum(1 for q in range(w.L - 4) if stats[q]["right_env_nodes"]) + \
         (1 if any(stats[q]["right_env_nodes"] for q in range(max(w.L - 4, 0), w.L)) else 0) + \
         sum(1 for q in range(2, w.L + 2) if stats[q]["left_env_nodes"])
+    if outer_from_level_above(w):  # right level 0 (its own launch when L > 4), left L+1
+        env_levels -= (1 if w.L > 4 else 0) + 1
     dom = max(models, key=lambda k: kern[k][0])
     dom_ms, dom_launches = kern[dom]
     per_launch = max(dom_launches // args.steps, 1)   # launches per sweep
