@@ -852,10 +852,12 @@ bfc_status bfc_batch_sweep(bfc_batch* b, void* hip_stream) {
   } else {
     BFC_TRY(launch_batch(b->sweep, b->prec, st));
   }
-  // as after a single sweep: every right level is stale, every left level current
+  // as after a single sweep: every right level is stale, every left level
+  // current but the last one where the last core's update formed it itself
   for (bfc::Problem* P : b->probs) {
     for (auto& E : P->rlev) E.valid = false;
     for (size_t q = 2; q < P->llev.size(); ++q) P->llev[q].valid = true;
+    if (P->lay[P->L + 1].up_node) P->llev[P->L + 1].valid = false;
     P->fused_res_valid = true;
   }
   return BFC_OK;

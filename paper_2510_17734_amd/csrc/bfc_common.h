@@ -220,8 +220,11 @@ int64_t debug_fail_allocation_after(int64_t count);
 // One launch of a batched sweep: a kernel kind at one rank, over tasks (one
 // per problem taking part) whose argument structs and block prefix table live
 // in device memory.
+// BK_OUTER_UP1 / BK_OUTER_UP2: the outer updates of core 0 / core L+1 that
+// form their entries' environments from the level above (CoreLayout::up_node)
 enum { BK_ENV_RIGHT = 0, BK_ENV_LEFT = 1, BK_OUTER = 2, BK_GRAM_ROW = 3, BK_GRAM_COL = 4,
-       BK_SOLVE = 5, BK_RES = 6, BK_RES_FINAL = 7, BK_RES_FUSED = 8 };
+       BK_SOLVE = 5, BK_RES = 6, BK_RES_FINAL = 7, BK_RES_FUSED = 8, BK_OUTER_UP1 = 9,
+       BK_OUTER_UP2 = 10 };
 struct BatchLaunch {
   int kind = 0, r = 0;
   void* tasks = nullptr;        // device array of argument structs

@@ -401,12 +401,12 @@ __global__ __launch_bounds__(kOuterThreads) void outer_update_kernel(OuterArgs<T
   outer_update_body<T, R, UP>(A, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
-template <typename T, int R>
+template <typename T, int R, int UP>
 __global__ __launch_bounds__(kOuterThreads) void outer_update_kernel_batched(const OuterArgs<T>* tasks, const int32_t* block_off,
     int ntasks) {
   const int b = xcd_swizzle(blockIdx.x, gridDim.x);
   const int t = find_task(block_off, ntasks, b);
-  outer_update_body<T, R>(tasks[t], b - block_off[t]);
+  outer_update_body<T, R, UP>(tasks[t], b - block_off[t]);
 }
 
 
@@ -2516,9 +2516,14 @@ struct BatchStep {
                   std::vector<int64_t>& b) {
     const EnvLevel& E = right ? P->rlev[q] : P->llev[q];
     if (E.count <= 0) return;
+    // formed by the outer update next to it instead (up_node)
+    if (right ? (q == 0 && P->lay[0].up_node) : (q == P->L + 1 && P->lay[P->L + 1].up_node))
+      return;
     a.push_back(env_args<T, R>(P, q, right));
     b.push_back(grid_for(E.count));
   }
+  // the outer update of core p; with up_node it forms the outermost level's
+  // products itself (a BK_OUTER_UP1 / UP2 task), else it reads that level
   static void outer(const Problem* P, int p, std::vector<OuterArgs<T>>& a,
                     std::vector<int64_t>& b) {
     const int L = P->L;
@@ -2527,7 +2532,12 @@ struct BatchStep {
     cx<T>* fibers = cores + (p == 0 ? 0 : last_off(P->n, L, R));
     const cx<T>* env;
     const int32_t* idx;
-    if (p == 0) {
+    const cx<T>* zsl = nullptr;
+    if (C.up_node) {
+      env = p == 0 ? (const cx<T>*)P->rlev[1].vec : (const cx<T>*)P->llev[L].vec;
+      idx = C.up_node;
+      zsl = cores + inner_off(P->n, L, R, p == 0 ? 1 : L);
+    } else if (p == 0) {
       env = (L == 0) ? cores + last_off(P->n, L, R) : (const cx<T>*)P->rlev[0].vec;
       idx = (L == 0) ? C.cols : C.rnode;
     } else {
@@ -2537,7 +2547,7 @@ struct BatchStep {
     a.push_back(OuterArgs<T>{fibers, env, idx, (const cx<T>*)C.vals, C.blk_off, C.nblocks,
                              P->cfg.reg_rel, reg_floor_of(P),
                              P->cfg.reg_mode == BFC_REG_PROXIMAL ? 1 : 0, P->flags,
-                             p == L + 1 ? P->fused_res : nullptr, nullptr, L, P->c});
+                             p == L + 1 ? P->fused_res : nullptr, zsl, L, P->c});
     b.push_back(((int64_t)C.nblocks * 16 + kOuterThreads - 1) / kOuterThreads);
   }
   static void inner(const Problem* P, int p, std::vector<GramArgs<T>>& grow,
@@ -2612,11 +2622,18 @@ struct BatchPlanR {
       return upload_tasks<T>(B, BK_SOLVE, R, sv, bs);
     }
     if (phase == 3) {  // outer core 0 (step 0) or L+1 (step = L+1)
-      std::vector<OuterArgs<T>> a;
-      std::vector<int64_t> b;
-      for (Problem* P : ps)
-        if (step == 0 || step == P->L + 1) S::outer(P, step, a, b);
-      return upload_tasks<T>(B, BK_OUTER, R, a, b);
+      std::vector<OuterArgs<T>> a, au;
+      std::vector<int64_t> b, bu;
+      for (Problem* P : ps) {
+        const int p = step == 0 ? 0 : step;
+        if (step != 0 && step != P->L + 1) continue;
+        if (P->lay[p].up_node)
+          S::outer(P, p, au, bu);
+        else
+          S::outer(P, p, a, b);
+      }
+      BFC_TRY(upload_tasks<T>(B, BK_OUTER, R, a, b));
+      return upload_tasks<T>(B, step == 0 ? BK_OUTER_UP1 : BK_OUTER_UP2, R, au, bu);
     }
     // phase 4: residual norms
     std::vector<ResObsArgs<T>> a;
@@ -2691,7 +2708,15 @@ bfc_status launch_batched_r(const BatchLaunch& bl, hipStream_t st) {
                                                      bl.ntasks);
       break;
     case BK_OUTER:
-      outer_update_kernel_batched<T, R><<<g, kOuterThreads, 0, st>>>(
+      outer_update_kernel_batched<T, R, 0><<<g, kOuterThreads, 0, st>>>(
+          (const OuterArgs<T>*)bl.tasks, bl.block_off, bl.ntasks);
+      break;
+    case BK_OUTER_UP1:
+      outer_update_kernel_batched<T, R, 1><<<g, kOuterThreads, 0, st>>>(
+          (const OuterArgs<T>*)bl.tasks, bl.block_off, bl.ntasks);
+      break;
+    case BK_OUTER_UP2:
+      outer_update_kernel_batched<T, R, 2><<<g, kOuterThreads, 0, st>>>(
           (const OuterArgs<T>*)bl.tasks, bl.block_off, bl.ntasks);
       break;
     case BK_GRAM_ROW:
