@@ -98,9 +98,10 @@ SHAPES = [
     (64, 3, 2, 1500),
     (96, 3, 3, 2500),      # c = 12, not a power of two
     (128, 4, 5, 4000),
-    (64, 2, 6, 3000),
+    (64, 2, 6, 3000),      # L = 2: the outer updates form the outermost levels from level 1 / L
     (128, 3, 7, 9000),
     (128, 3, 8, 6000),
+    (64, 1, 3, 1200),      # L = 1: no level above, the outer updates read stored environments
 ]
 
 
